@@ -1,0 +1,246 @@
+"""FP64 CPU oracle for the super-droplet coalescence step -- TEST INFRASTRUCTURE ONLY.
+
+Loads ``sdm_oracle.c`` (built with gcc, ``-O2 -ffp-contract=off``) through ctypes and
+offers the whole-run helpers the tests use.  Only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import this package; the HIP library
+never does, and this package imports nothing from it.
+
+The method follows the Coalescence subsection (Sect. 5.1.4) of the libcloudph++ 0.2
+paper: random non-overlapping pairs per cell and sub-step, the collision probability of
+eq. (P_ij), comparison against a uniform deviate on (0,1), and the multiplicity / radius
+bookkeeping of a collision event, extended by multiple coalescence with the gamma cap.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sdm_oracle.c")
+_BUILD_DIR = os.path.join(_HERE, "_build")
+_LIB_PATH = os.path.join(_BUILD_DIR, "libsdm_oracle.so")
+
+GOLOVIN = 0
+GEOMETRIC = 1
+
+# Default kernel parameters: Golovin b = 1500 s^-1; terminal velocity after
+# Rogers & Yau (1989) in SI units (k1 r^2 below 40 um, k2 r up to 600 um,
+# k3 sqrt(r) above); collection efficiency E = 1.
+DEFAULT_PARAMS = (1500.0, 1.19e8, 8.0e3, 201.0, 40e-6, 600e-6, 1.0)
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle shared library with gcc (no fast-math, no FP contraction)."""
+    os.makedirs(_BUILD_DIR, exist_ok=True)
+    if (not force and os.path.exists(_LIB_PATH)
+            and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC)):
+        return _LIB_PATH
+    tmp = _LIB_PATH + f".tmp{os.getpid()}"
+    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = build()
+    L = ctypes.CDLL(path)
+    u32, u64, dbl, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, ctypes.c_int
+    P = ctypes.c_void_p
+    L.oracle_philox4x32_10.argtypes = [P, P, P]
+    L.oracle_philox4x32_10.restype = None
+    L.oracle_shuffle_key.argtypes = [u64, u32, u32, u32]
+    L.oracle_shuffle_key.restype = u32
+    L.oracle_pair_uniform.argtypes = [u64, u32, u32, u32]
+    L.oracle_pair_uniform.restype = dbl
+    L.oracle_cbrt_rn.argtypes = [dbl]
+    L.oracle_cbrt_rn.restype = dbl
+    L.oracle_terminal_velocity.argtypes = [P, dbl]
+    L.oracle_terminal_velocity.restype = dbl
+    L.oracle_kernel.argtypes = [i32, P, dbl, dbl]
+    L.oracle_kernel.restype = dbl
+    L.oracle_upscale.argtypes = [u32]
+    L.oracle_upscale.restype = dbl
+    L.oracle_probability.argtypes = [u64, dbl, dbl, dbl, dbl]
+    L.oracle_probability.restype = dbl
+    L.oracle_gamma.argtypes = [dbl, dbl, u64, u64]
+    L.oracle_gamma.restype = u64
+    L.oracle_collide_pair.argtypes = [u64, P, P, P, P]
+    L.oracle_collide_pair.restype = None
+    L.oracle_cell_order.argtypes = [u32, P, u64, u32, u32, P]
+    L.oracle_cell_order.restype = u32
+    L.oracle_step.argtypes = [u32, P, P, P, P, dbl, i32, P, u64, u32, u32, P]
+    L.oracle_step.restype = i32
+    L.oracle_sort_by_cell.argtypes = [u64, P, u32, P, P]
+    L.oracle_sort_by_cell.restype = i32
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def _params(params) -> np.ndarray:
+    p = np.asarray(DEFAULT_PARAMS if params is None else params, dtype=np.float64)
+    assert p.shape == (7,)
+    return np.ascontiguousarray(p)
+
+
+# ---------------------------------------------------------------- primitives
+def philox4x32_10(ctr, key) -> tuple:
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return tuple(int(v) for v in out)
+
+
+def shuffle_key(seed: int, cell: int, step: int, slot: int) -> int:
+    return int(lib().oracle_shuffle_key(seed, cell, step, slot))
+
+
+def pair_uniform(seed: int, cell: int, step: int, m: int) -> float:
+    return float(lib().oracle_pair_uniform(seed, cell, step, m))
+
+
+def cbrt_rn(x: float) -> float:
+    return float(lib().oracle_cbrt_rn(x))
+
+
+def terminal_velocity(r: float, params=None) -> float:
+    p = _params(params)
+    return float(lib().oracle_terminal_velocity(_ptr(p), r))
+
+
+def kernel(kind: int, ra: float, rb: float, params=None) -> float:
+    p = _params(params)
+    return float(lib().oracle_kernel(kind, _ptr(p), ra, rb))
+
+
+def upscale(n: int) -> float:
+    return float(lib().oracle_upscale(n))
+
+
+def probability(xi_max: int, K: float, dt: float, dV: float, scale: float) -> float:
+    return float(lib().oracle_probability(xi_max, K, dt, dV, scale))
+
+
+def gamma(p: float, u: float, xi_j: int, xi_k: int) -> int:
+    return int(lib().oracle_gamma(p, u, xi_j, xi_k))
+
+
+def collide_pair(g: int, xi_j: int, r_j: float, xi_k: int, r_k: float):
+    a = np.array([xi_j, xi_k], dtype=np.uint64)
+    r = np.array([r_j, r_k], dtype=np.float64)
+    lib().oracle_collide_pair(g, a.ctypes.data, r.ctypes.data, a.ctypes.data + 8,
+                              r.ctypes.data + 8)
+    return int(a[0]), float(r[0]), int(a[1]), float(r[1])
+
+
+def cell_order(xi_cell: np.ndarray, seed: int, cell: int, step: int) -> np.ndarray:
+    xi_cell = np.ascontiguousarray(xi_cell, dtype=np.uint64)
+    order = np.zeros(max(1, xi_cell.size), dtype=np.uint32)
+    n = lib().oracle_cell_order(xi_cell.size, _ptr(xi_cell), seed, cell, step, _ptr(order))
+    return order[:n].copy()
+
+
+# ---------------------------------------------------------------- whole runs
+class SlotState:
+    """Super-droplets in canonical storage order: stable-sorted by cell."""
+
+    def __init__(self, cell, xi, r, dV):
+        cell = np.ascontiguousarray(cell, dtype=np.uint32)
+        self.n_cells = int(len(dV))
+        self.dV = np.ascontiguousarray(dV, dtype=np.float64)
+        self.offsets = np.zeros(self.n_cells + 1, dtype=np.uint64)
+        self.id = np.zeros(cell.size, dtype=np.uint64)
+        rc = lib().oracle_sort_by_cell(cell.size, _ptr(cell), self.n_cells,
+                                       _ptr(self.offsets), _ptr(self.id))
+        if rc != 0:
+            raise ValueError("cell index out of range")
+        idx = self.id.astype(np.int64)
+        self.xi = np.ascontiguousarray(np.asarray(xi, dtype=np.uint64)[idx])
+        self.r = np.ascontiguousarray(np.asarray(r, dtype=np.float64)[idx])
+        self.stats = np.zeros(2, dtype=np.uint64)
+
+    def step(self, dt: float, kind: int, seed: int, step: int, params=None,
+             cells: tuple | None = None, cell_index_base: int = 0):
+        """One coalescence step over all cells, or over the cell range ``cells``."""
+        p = _params(params)
+        c0, c1 = (0, self.n_cells) if cells is None else cells
+        off = np.ascontiguousarray(self.offsets[c0:c1 + 1])
+        dv = np.ascontiguousarray(self.dV[c0:c1])
+        base = int(off[0]) if off.size else 0
+        # slices of xi / r starting at the first slot of cell c0, offsets rebased
+        rel = np.ascontiguousarray(off - np.uint64(base))
+        xi_view = self.xi[base:]
+        r_view = self.r[base:]
+        st = np.zeros(2, dtype=np.uint64)
+        lib().oracle_step(c1 - c0, _ptr(rel), _ptr(dv), xi_view.ctypes.data,
+                          r_view.ctypes.data, dt, kind, _ptr(p), seed, step,
+                          cell_index_base + c0, _ptr(st))
+        self.stats += st
+        return st
+
+    def step_parallel(self, dt, kind, seed, step, params=None, threads: int = 8):
+        """Same result as ``step``: cells are independent, so ranges of cells run
+        in separate threads (ctypes releases the GIL)."""
+        n = self.n_cells
+        if threads <= 1 or n < 2 * threads:
+            return self.step(dt, kind, seed, step, params)
+        bounds = np.linspace(0, n, threads + 1).astype(int)
+        parts = [(int(bounds[i]), int(bounds[i + 1])) for i in range(threads)]
+        with ThreadPoolExecutor(threads) as ex:
+            res = list(ex.map(lambda cr: self._step_range(dt, kind, seed, step, params, cr),
+                              parts))
+        st = np.sum(res, axis=0).astype(np.uint64)
+        self.stats += st
+        return st
+
+    def _step_range(self, dt, kind, seed, step, params, cr):
+        p = _params(params)
+        c0, c1 = cr
+        off = np.ascontiguousarray(self.offsets[c0:c1 + 1])
+        dv = np.ascontiguousarray(self.dV[c0:c1])
+        base = int(off[0])
+        rel = np.ascontiguousarray(off - np.uint64(base))
+        st = np.zeros(2, dtype=np.uint64)
+        lib().oracle_step(c1 - c0, _ptr(rel), _ptr(dv), self.xi[base:].ctypes.data,
+                          self.r[base:].ctypes.data, dt, kind, _ptr(p), seed, step, c0,
+                          _ptr(st))
+        return st
+
+    def input_order(self):
+        """(xi, r) scattered back to input order."""
+        xi = np.empty_like(self.xi)
+        r = np.empty_like(self.r)
+        idx = self.id.astype(np.int64)
+        xi[idx] = self.xi
+        r[idx] = self.r
+        return xi, r
+
+
+def run(cell, xi, r, dV, steps: int, dt: float, kind: int, seed: int,
+        first_step: int = 0, params=None, threads: int = 1):
+    """Run ``steps`` coalescence steps (step numbers first_step, first_step+1, ...)
+    and return (xi, r, stats) in input order."""
+    st = SlotState(cell, xi, r, dV)
+    for t in range(first_step, first_step + steps):
+        if threads > 1:
+            st.step_parallel(dt, kind, seed, t, params, threads)
+        else:
+            st.step(dt, kind, seed, t, params)
+    xo, ro = st.input_order()
+    return xo, ro, st.stats.copy()

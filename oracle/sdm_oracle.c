@@ -1,0 +1,430 @@
+/*
+ * sdm_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct FP64 CPU implementation of one Monte-Carlo
+ * coalescence step of the Super-Droplet Method (SDM), as the particle-based
+ * scheme of libcloudph++ 0.2 (Arabas, Jaruga, Pawlowska, Grabowski) states it
+ * in Sect. 5.1.4 "Coalescence", eq. (P_ij), extended by multiple coalescence
+ * with the gamma-capping rule (see oracle_collide_pair).
+ *
+ * It exists to check the HIP library.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no code, header,
+ * table or constant generator with the HIP library and includes nothing from it.
+ *
+ * Build: gcc -O2 -ffp-contract=off (no fast-math) so that every floating-point
+ * operation below is one IEEE-754 binary64 operation in the written order.
+ *
+ * Readings of the paper taken here (the paper is silent or differs):
+ *   - n in eq. (P_ij) = number of super-droplets with multiplicity > 0 in the
+ *     cell at the start of the step;
+ *   - random grouping into non-overlapping pairs = sort the live storage slots
+ *     by (32-bit Philox key, slot) and pair neighbours (2m, 2m+1);
+ *   - "larger multiplicity" on a tie = the first member of the pair;
+ *   - the super-droplet with the smaller multiplicity keeps it and takes the
+ *     merged radius, the larger one keeps its radius and loses gamma*xi_k
+ *     (the mass-conserving reading of the outcome described in Sect. 5.1.4);
+ *   - equal multiplicities after the collision split xi_k in two halves
+ *     (instead of leaving a zero-multiplicity particle for recycling);
+ *   - random numbers from counter-based Philox4x32-10 instead of the
+ *     Mersenne Twister the paper's release uses (Sect. 5.3).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* binary64 nearest to pi */
+static const double ORACLE_PI = 3.141592653589793238462643383279502884;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplications,     */
+/* with the key incremented by two Weyl constants between rounds.            */
+/* ------------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ x1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ x3 ^ k1;
+        uint32_t n3 = lo0;
+        x0 = n0; x1 = n1; x2 = n2; x3 = n3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Shuffle key of storage slot s of cell c at step t: word (s mod 4) of
+ * Philox(counter = (s div 4, c, t, 0), key = (seed low, seed high)). */
+uint32_t oracle_shuffle_key(uint64_t seed, uint32_t cell, uint32_t step, uint32_t slot)
+{
+    uint32_t ctr[4] = {slot / 4u, cell, step, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    oracle_philox4x32_10(ctr, key, w);
+    return w[slot % 4u];
+}
+
+/* Uniform deviate on the open interval (0,1) for pair m of cell c at step t:
+ * two words of Philox(counter = (m div 2, c, t, 1)) give a 64-bit integer
+ * (first word high); its top 52 bits k give u = (2k+1)/2^53, which is exact
+ * in binary64 and never 0 or 1. */
+double oracle_pair_uniform(uint64_t seed, uint32_t cell, uint32_t step, uint32_t m)
+{
+    uint32_t ctr[4] = {m / 2u, cell, step, 1u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    oracle_philox4x32_10(ctr, key, w);
+    uint32_t hi = w[2u * (m % 2u)];
+    uint32_t lo = w[2u * (m % 2u) + 1u];
+    uint64_t word = ((uint64_t)hi << 32) | (uint64_t)lo;
+    uint64_t k = word >> 12;
+    return (double)(2u * k + 1u) * 0x1p-53;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Correctly rounded cube root.  y is the cube root of x rounded to nearest  */
+/* iff the exact cubes of the two midpoints around y bracket x.  The test is  */
+/* done exactly with 32-bit-limb integers.                                   */
+/* ------------------------------------------------------------------------ */
+#define BIG_LIMBS 16
+typedef struct { uint32_t d[BIG_LIMBS]; } big_t; /* little-endian limbs */
+
+static void big_from_u64(big_t *a, uint64_t v)
+{
+    memset(a, 0, sizeof(*a));
+    a->d[0] = (uint32_t)v;
+    a->d[1] = (uint32_t)(v >> 32);
+}
+
+static void big_mul_u64(big_t *a, uint64_t v)
+{
+    /* a <- a * v, schoolbook on 32-bit limbs */
+    uint32_t v0 = (uint32_t)v, v1 = (uint32_t)(v >> 32);
+    big_t r;
+    memset(&r, 0, sizeof(r));
+    for (int i = 0; i < BIG_LIMBS; ++i) {
+        uint64_t carry = 0;
+        for (int j = 0; j < 2; ++j) {
+            uint32_t vj = j == 0 ? v0 : v1;
+            if (i + j >= BIG_LIMBS) break;
+            uint64_t t = (uint64_t)a->d[i] * vj + r.d[i + j] + carry;
+            r.d[i + j] = (uint32_t)t;
+            carry = t >> 32;
+        }
+        /* propagate the remaining carry */
+        for (int k = i + 2; carry != 0 && k < BIG_LIMBS; ++k) {
+            uint64_t t = (uint64_t)r.d[k] + carry;
+            r.d[k] = (uint32_t)t;
+            carry = t >> 32;
+        }
+    }
+    *a = r;
+}
+
+static void big_shl(big_t *a, int bits)
+{
+    big_t r;
+    memset(&r, 0, sizeof(r));
+    int limbs = bits / 32, rem = bits % 32;
+    for (int i = BIG_LIMBS - 1; i >= 0; --i) {
+        int src = i - limbs;
+        if (src < 0) continue;
+        uint64_t v = (uint64_t)a->d[src] << rem;
+        if (rem != 0 && src - 1 >= 0) v |= (uint64_t)a->d[src - 1] >> (32 - rem);
+        r.d[i] = (uint32_t)v;
+    }
+    *a = r;
+}
+
+static int big_cmp(const big_t *a, const big_t *b)
+{
+    for (int i = BIG_LIMBS - 1; i >= 0; --i) {
+        if (a->d[i] != b->d[i]) return a->d[i] < b->d[i] ? -1 : 1;
+    }
+    return 0;
+}
+
+static int bitlen_u64(uint64_t v)
+{
+    int n = 0;
+    while (v) { ++n; v >>= 1; }
+    return n;
+}
+
+/* Sign of (M * 2^em)^3 - X * 2^ex for M, X > 0 (M < 2^56, X < 2^54). */
+static int cube_cmp(uint64_t M, int em, uint64_t X, int ex)
+{
+    big_t c, x;
+    big_from_u64(&c, M);
+    big_mul_u64(&c, M);
+    big_mul_u64(&c, M);
+    big_from_u64(&x, X);
+    int ec = 3 * em;
+    /* bit lengths of both values as exponents of 2 */
+    int lc = 0;
+    for (int i = BIG_LIMBS - 1; i >= 0; --i) {
+        if (c.d[i]) { lc = 32 * i + bitlen_u64(c.d[i]); break; }
+    }
+    int lx = bitlen_u64(X);
+    if (lc + ec != lx + ex) return (lc + ec > lx + ex) ? 1 : -1;
+    /* same magnitude: align the exponents (the shift is below 3*56 bits) */
+    if (ec > ex) big_shl(&c, ec - ex);
+    else if (ex > ec) big_shl(&x, ex - ec);
+    return big_cmp(&c, &x);
+}
+
+/* positive finite normal double -> (Y, e) with d = Y * 2^e, 2^52 <= Y < 2^53 */
+static void split_normal(double d, uint64_t *Y, int *e)
+{
+    int ex;
+    double f = frexp(d, &ex);          /* d = f * 2^ex, 0.5 <= f < 1 */
+    *Y = (uint64_t)ldexp(f, 53);
+    *e = ex - 53;
+}
+
+/* positive finite double (normal or subnormal) -> (X, e) with d = X * 2^e */
+static void split_any(double d, uint64_t *X, int *e)
+{
+    int ex;
+    double f = frexp(d, &ex);
+    *X = (uint64_t)ldexp(f, 53);
+    *e = ex - 53;
+}
+
+/* midpoint between two adjacent positive normal doubles a < b, as M * 2^em */
+static void midpoint(double a, double b, uint64_t *M, int *em)
+{
+    uint64_t A, B;
+    int ea, eb;
+    split_normal(a, &A, &ea);
+    split_normal(b, &B, &eb);
+    int e = ea < eb ? ea : eb;
+    uint64_t s = (A << (ea - e)) + (B << (eb - e)); /* both below 2^55 */
+    *M = s;
+    *em = e - 1;
+}
+
+double oracle_cbrt_rn(double x)
+{
+    if (x != x || x == 0.0 || isinf(x)) return x;
+    if (x < 0.0) return -oracle_cbrt_rn(-x);
+    uint64_t X;
+    int ex;
+    split_any(x, &X, &ex);
+    double y = cbrt(x);                /* within a few ulp; corrected below */
+    for (int guard = 0; guard < 64; ++guard) {
+        double up = nextafter(y, INFINITY);
+        double dn = nextafter(y, 0.0);
+        uint64_t M;
+        int em;
+        midpoint(y, up, &M, &em);
+        if (cube_cmp(M, em, X, ex) < 0) { y = up; continue; }   /* cbrt(x) above the upper midpoint */
+        midpoint(dn, y, &M, &em);
+        if (cube_cmp(M, em, X, ex) > 0) { y = dn; continue; }   /* below the lower midpoint */
+        return y;
+    }
+    return y; /* not reached for finite positive x */
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collection kernels                                                        */
+/* ------------------------------------------------------------------------ */
+enum { ORACLE_GOLOVIN = 0, ORACLE_GEOMETRIC = 1 };
+
+/* params: [0] Golovin b (s^-1), [1] k1 (m^-1 s^-1), [2] k2 (s^-1),
+ *         [3] k3 (m^1/2 s^-1), [4] r1 (m), [5] r2 (m), [6] efficiency E */
+
+/* piecewise terminal velocity: Stokes k1 r^2 below r1, k2 r up to and
+ * including r2, k3 sqrt(r) above r2 */
+double oracle_terminal_velocity(const double *params, double r)
+{
+    if (r < params[4]) return params[1] * (r * r);
+    if (r <= params[5]) return params[2] * r;
+    return params[3] * sqrt(r);
+}
+
+/* Golovin kernel K = b (v_a + v_b) with v = (4 pi / 3) r^3 (droplet volume). */
+static double golovin_kernel(const double *params, double ra, double rb)
+{
+    const double four_pi_over_3 = (4.0 * ORACLE_PI) / 3.0;
+    double va = four_pi_over_3 * ((ra * ra) * ra);
+    double vb = four_pi_over_3 * ((rb * rb) * rb);
+    return params[0] * (va + vb);
+}
+
+/* Geometric kernel of Sect. 5.1.4: K = E pi (r_a + r_b)^2 |v_a - v_b|. */
+static double geometric_kernel(const double *params, double ra, double rb)
+{
+    double sum = ra + rb;
+    double area = ORACLE_PI * (sum * sum);
+    double dv = fabs(oracle_terminal_velocity(params, ra) - oracle_terminal_velocity(params, rb));
+    return (params[6] * area) * dv;
+}
+
+double oracle_kernel(int kind, const double *params, double ra, double rb)
+{
+    return kind == ORACLE_GOLOVIN ? golovin_kernel(params, ra, rb) : geometric_kernel(params, ra, rb);
+}
+
+/* Upscaling factor of eq. (P_ij): n(n-1)/2 candidate pairs over floor(n/2) examined ones. */
+double oracle_upscale(uint32_t n)
+{
+    uint64_t all_pairs = (uint64_t)n * (uint64_t)(n - 1u) / 2u;
+    uint64_t examined = (uint64_t)(n / 2u);
+    return (double)all_pairs / (double)examined;
+}
+
+/* eq. (P_ij): p = max(xi_a, xi_b) K dt / dV * scale, evaluated in this order. */
+double oracle_probability(uint64_t xi_max, double K, double dt, double dV, double scale)
+{
+    double p = (double)xi_max * K;
+    p = p * dt;
+    p = p / dV;
+    p = p * scale;
+    return p;
+}
+
+/* Number of collision events gamma for one pair: floor(p) plus a Bernoulli
+ * draw of the fractional part against u, capped at floor(xi_j / xi_k) so the
+ * larger super-droplet can supply all of them.  With p < 1 and no binding
+ * cap this is the paper's rule "collide iff p > u". */
+uint64_t oracle_gamma(double p, double u, uint64_t xi_j, uint64_t xi_k)
+{
+    uint64_t cap = xi_j / xi_k;
+    double fl = floor(p);
+    double frac = p - fl;
+    if (fl >= (double)cap) return cap;
+    uint64_t g = (uint64_t)fl + (u < frac ? 1u : 0u);
+    return g < cap ? g : cap;
+}
+
+/* Apply gamma collision events between super-droplets j (larger or equal
+ * multiplicity) and k.  gamma * xi_k droplets of j merge with the xi_k
+ * droplets of k, gamma at a time, so k keeps xi_k and takes the merged radius
+ * while j keeps its radius and loses gamma * xi_k.  If that would leave j
+ * empty, the xi_k merged droplets are split between both super-droplets. */
+void oracle_collide_pair(uint64_t g, uint64_t *xi_j, double *r_j, uint64_t *xi_k, double *r_k)
+{
+    if (g == 0) return;
+    double rj3 = (*r_j * *r_j) * *r_j;
+    double rk3 = (*r_k * *r_k) * *r_k;
+    double vol = (double)g * rj3;
+    vol = vol + rk3;
+    double r_new = oracle_cbrt_rn(vol);
+    uint64_t removed = g * *xi_k;
+    if (*xi_j > removed) {
+        *xi_j = *xi_j - removed;
+        *r_k = r_new;
+    } else {
+        uint64_t half = *xi_k / 2u;
+        *xi_j = half;
+        *xi_k = *xi_k - half;
+        *r_j = r_new;
+        *r_k = r_new;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random grouping into non-overlapping pairs                                */
+/* ------------------------------------------------------------------------ */
+typedef struct { uint32_t key; uint32_t slot; } keyed_slot;
+
+static int cmp_keyed_slot(const void *pa, const void *pb)
+{
+    const keyed_slot *a = (const keyed_slot *)pa, *b = (const keyed_slot *)pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    if (a->slot != b->slot) return a->slot < b->slot ? -1 : 1;
+    return 0;
+}
+
+/* Order of the live slots (xi > 0) of one cell for step t: ascending by
+ * (shuffle key, slot).  Returns the number n of live slots; order[0..n). */
+uint32_t oracle_cell_order(uint32_t n_slots, const uint64_t *xi, uint64_t seed,
+                           uint32_t cell, uint32_t step, uint32_t *order)
+{
+    keyed_slot *buf = (keyed_slot *)malloc(sizeof(keyed_slot) * (n_slots ? n_slots : 1));
+    uint32_t n = 0;
+    for (uint32_t s = 0; s < n_slots; ++s) {
+        if (xi[s] == 0) continue;
+        buf[n].key = oracle_shuffle_key(seed, cell, step, s);
+        buf[n].slot = s;
+        ++n;
+    }
+    qsort(buf, n, sizeof(keyed_slot), cmp_keyed_slot);
+    for (uint32_t i = 0; i < n; ++i) order[i] = buf[i].slot;
+    free(buf);
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One coalescence step                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* One step over cells [0, n_cells) stored slot-contiguously: cell c owns
+ * slots [offsets[c], offsets[c+1]).  The RNG cell index of cell c is
+ * cell_index_base + c.  stats[0] += pair tests, stats[1] += collisions. */
+int oracle_step(uint32_t n_cells, const uint64_t *offsets, const double *dV,
+                uint64_t *xi, double *r, double dt, int kernel, const double *params,
+                uint64_t seed, uint32_t step, uint32_t cell_index_base, uint64_t *stats)
+{
+    uint32_t max_slots = 0;
+    for (uint32_t c = 0; c < n_cells; ++c) {
+        uint64_t cnt = offsets[c + 1] - offsets[c];
+        if (cnt > max_slots) max_slots = (uint32_t)cnt;
+    }
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (max_slots ? max_slots : 1));
+    for (uint32_t c = 0; c < n_cells; ++c) {
+        uint64_t base = offsets[c];
+        uint32_t n_slots = (uint32_t)(offsets[c + 1] - base);
+        uint32_t cell = cell_index_base + c;
+        uint32_t n = oracle_cell_order(n_slots, xi + base, seed, cell, step, order);
+        if (n < 2) continue;
+        double scale = oracle_upscale(n);
+        for (uint32_t m = 0; m < n / 2u; ++m) {
+            uint64_t a = base + order[2u * m];
+            uint64_t b = base + order[2u * m + 1u];
+            uint64_t j = xi[a] >= xi[b] ? a : b;   /* tie: first member is j */
+            uint64_t k = j == a ? b : a;
+            double K = oracle_kernel(kernel, params, r[a], r[b]);
+            double p = oracle_probability(xi[j], K, dt, dV[c], scale);
+            double u = oracle_pair_uniform(seed, cell, step, m);
+            uint64_t g = oracle_gamma(p, u, xi[j], xi[k]);
+            if (g > 0) stats[1] += 1;
+            oracle_collide_pair(g, &xi[j], &r[j], &xi[k], &r[k]);
+        }
+        stats[0] += n / 2u;
+    }
+    free(order);
+    return 0;
+}
+
+/* Stable sort of super-droplets by cell (ties in input order).  Writes the
+ * slot offsets (n_cells + 1) and id[slot] = input index.  Returns -1 if a
+ * cell index is out of range. */
+int oracle_sort_by_cell(uint64_t n_sd, const uint32_t *cell, uint32_t n_cells,
+                        uint64_t *offsets, uint64_t *id)
+{
+    for (uint64_t i = 0; i < n_sd; ++i)
+        if (cell[i] >= n_cells) return -1;
+    uint64_t *fill = (uint64_t *)calloc((size_t)n_cells + 1u, sizeof(uint64_t));
+    memset(offsets, 0, sizeof(uint64_t) * ((size_t)n_cells + 1u));
+    for (uint64_t i = 0; i < n_sd; ++i) offsets[cell[i] + 1u] += 1u;
+    for (uint32_t c = 0; c < n_cells; ++c) offsets[c + 1u] += offsets[c];
+    for (uint64_t i = 0; i < n_sd; ++i) {
+        uint32_t c = cell[i];
+        id[offsets[c] + fill[c]] = i;
+        fill[c] += 1u;
+    }
+    free(fill);
+    return 0;
+}
