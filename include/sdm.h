@@ -1,0 +1,267 @@
+/*
+ * sdm.h -- C ABI of the MI355X (gfx950) super-droplet coalescence library.
+ *
+ * The library advances the Monte-Carlo coalescence of super-droplets within
+ * grid cells, one time step per call, as the particle-based scheme of
+ * libcloudph++ 0.2 (Arabas et al.) describes it in Sect. 5.1.4 (Coalescence):
+ *
+ *   - per cell and step, the super-droplets (SDs) with multiplicity xi > 0 are
+ *     grouped at random into floor(n/2) non-overlapping pairs;
+ *   - each pair (a, b) collides with the probability of eq. (P_ij)
+ *         p = max(xi_a, xi_b) K(r_a, r_b) dt / dV  *  n(n-1)/2 / floor(n/2),
+ *     where n is the number of live SDs in the cell and K the collection
+ *     kernel (geometric kernel of Sect. 5.1.4, or Golovin's kernel);
+ *   - the number of collision events is gamma = floor(p) + [u < p - floor(p)]
+ *     for a uniform deviate u on (0,1), capped at floor(xi_j / xi_k) where j
+ *     is the SD with the larger multiplicity (the first one on a tie);
+ *   - gamma*xi_k droplets of j merge with the xi_k droplets of k: k keeps xi_k
+ *     and takes r_k' = cbrt(gamma r_j^3 + r_k^3) (rounded to nearest), j keeps
+ *     r_j and loses gamma*xi_k; when that would empty j, both SDs take the
+ *     merged radius and share xi_k as floor(xi_k/2) (j) and the rest (k).
+ *
+ * Randomness is counter-based Philox4x32-10 keyed by (seed, step, cell, slot)
+ * (the paper's release uses Mersenne Twister, Sect. 5.3): the shuffle key of
+ * storage slot s of cell c at step t is word (s mod 4) of
+ * Philox(counter = (s/4, c, t, 0), key = (seed & 0xffffffff, seed >> 32));
+ * the live slots are ordered by (key, slot) and paired as (2m, 2m+1); pair m
+ * draws u = (2k+1) 2^-53 with k the top 52 bits of the 64-bit integer formed
+ * by words 2(m mod 2) (high) and 2(m mod 2)+1 (low) of
+ * Philox(counter = (m/2, c, t, 1), same key).
+ *
+ * Storage order: at initialisation the SDs are stable-sorted by cell (ties in
+ * input order); cell c then owns a fixed range of storage slots, local slot
+ * s = 0..N_c-1.  Results are therefore a function of (inputs, seed, step
+ * numbers) only: independent of launch shape, batching and mix.
+ *
+ * Conventions for every call:
+ *   - "dev" pointers are device (HBM) pointers on the current HIP device;
+ *     "host" pointers are host memory.  The caller owns every buffer it
+ *     passes, including the workspace; the library never allocates device
+ *     memory and frees none.
+ *   - stream arguments are hipStream_t values passed as void* (NULL = the
+ *     default stream).  All kernels of a context run on its stream.
+ *   - every call returns an sdm_status; no exception crosses the ABI.
+ *   - a context or batch is used by one host thread at a time; separate
+ *     contexts on separate streams are independent.
+ */
+#ifndef SDM_H_
+#define SDM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SDM_OK = 0,
+    SDM_EINVAL = -1,   /* invalid argument or input data */
+    SDM_ENOMEM = -2,   /* workspace too small / capacity exhausted */
+    SDM_EDEVICE = -3,  /* a HIP runtime call failed */
+    SDM_ESTATE = -4,   /* call not valid in the object's current state */
+    SDM_EBUDGET = -5   /* batch capacity (SDs, cells or instances) exhausted */
+} sdm_status;
+
+typedef enum {
+    SDM_KERNEL_GOLOVIN = 0,    /* K = b (v_a + v_b), v = (4 pi / 3) r^3 */
+    SDM_KERNEL_GEOMETRIC = 1   /* K = E pi (r_a + r_b)^2 |v_t(r_a) - v_t(r_b)|, Sect. 5.1.4 */
+} sdm_kernel;
+
+/* Collection-kernel parameters (SI units).  NULL wherever a pointer to this
+ * struct is accepted means the defaults given here. */
+typedef struct {
+    double golovin_b;   /* Golovin constant b, default 1500 s^-1 */
+    double vt_k1;       /* v_t = k1 r^2 for r < vt_r1, default 1.19e8 m^-1 s^-1 */
+    double vt_k2;       /* v_t = k2 r for vt_r1 <= r <= vt_r2, default 8.0e3 s^-1 */
+    double vt_k3;       /* v_t = k3 sqrt(r) for r > vt_r2, default 201.0 m^1/2 s^-1 */
+    double vt_r1;       /* default 40e-6 m */
+    double vt_r2;       /* default 600e-6 m */
+    double efficiency;  /* collection efficiency E, default 1 */
+} sdm_kernel_params;
+
+/* Fill *p with the defaults listed above. */
+void sdm_default_params(sdm_kernel_params *p);
+
+/* Text for a status code (static storage). */
+const char *sdm_strerror(sdm_status s);
+
+/* Message of the last failure on the calling thread (static thread-local storage). */
+const char *sdm_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Single run: one set of cells advanced by sdm_coalesce_step.               */
+/* ------------------------------------------------------------------------ */
+typedef struct sdm_ctx sdm_ctx;
+
+/* Bytes of device workspace sdm_init needs for n_sd SDs in n_cells cells. */
+size_t sdm_workspace_bytes(uint64_t n_sd, uint32_t n_cells);
+
+/* Create a context and copy the SDs into workspace-resident state.
+ *   stream     : hipStream_t (as void*) all work of the context runs on.
+ *   workspace  : dev, >= sdm_workspace_bytes(n_sd, n_cells) bytes, 256-byte
+ *                aligned; owned by the caller, must outlive the context.
+ *   n_sd       : number of SDs, < 2^32.
+ *   cell       : dev uint32[n_sd], cell index of each SD, < n_cells.
+ *   xi         : dev uint64[n_sd], multiplicity (0 = dead SD, never paired).
+ *   r          : dev double[n_sd], radius in metres, finite and > 0.
+ *   n_cells    : number of cells (>= 1 when n_sd > 0).
+ *   dV         : dev double[n_cells], cell volume in m^3, finite and > 0.
+ *   params     : host, nullable (defaults).
+ * The inputs may be freed after the call returns.  Synchronises the stream.
+ * Errors: SDM_EINVAL for a bad pointer/size, a cell index out of range, a
+ * radius or volume that is not finite and positive; SDM_ENOMEM if ws_bytes is
+ * too small; SDM_EDEVICE for a HIP failure.  *out is NULL on error. */
+sdm_status sdm_init(sdm_ctx **out, void *stream, void *workspace, size_t ws_bytes,
+                    uint64_t n_sd, const uint32_t *cell, const uint64_t *xi,
+                    const double *r, uint32_t n_cells, const double *dV,
+                    const sdm_kernel_params *params);
+
+/* Enqueue one coalescence step (Sect. 5.1.4) of every cell on the context's
+ * stream and return without waiting.  dt > 0 is the (sub)step length in s;
+ * step < 2^32 is the caller's step number, used only as the RNG counter (the
+ * same (seed, step) twice applies the same random draws twice).
+ * Errors: SDM_EINVAL (dt not finite and positive, unknown kernel,
+ * step >= 2^32), SDM_EDEVICE (launch failure). */
+sdm_status sdm_coalesce_step(sdm_ctx *ctx, double dt, sdm_kernel kernel, uint64_t seed,
+                             uint64_t step);
+
+/* Copy the current state back in input order: xi_out (dev uint64[n_sd]) and
+ * r_out (dev double[n_sd]), either may be NULL.  Synchronises the stream. */
+sdm_status sdm_get_state(sdm_ctx *ctx, uint64_t *xi_out, double *r_out);
+
+/* Totals since sdm_init: pair tests (sum over steps and cells of floor(n/2))
+ * and collisions (pairs with gamma > 0).  host outputs, nullable.
+ * Synchronises the stream. */
+sdm_status sdm_get_stats(sdm_ctx *ctx, uint64_t *pair_tests, uint64_t *collisions);
+
+/* Storage-order views for diagnostics: slot offsets (dev uint32[n_cells+1])
+ * and slot->input-index map (dev uint32[n_sd]).  Pointers into the workspace,
+ * valid while the context lives. */
+sdm_status sdm_get_layout(sdm_ctx *ctx, const uint32_t **offsets, const uint32_t **input_index);
+
+/* Compute, without changing the state, the pairing order step `step` would
+ * use: for each cell c, order_out[offsets[c] + i] (dev uint32[n_sd]) = local
+ * slot of the i-th live SD after the shuffle, i < n_live_out[c]
+ * (dev uint32[n_cells]).  Slots of order_out past n_live are left unchanged.
+ * Synchronises the stream. */
+sdm_status sdm_debug_permutation(sdm_ctx *ctx, uint64_t seed, uint64_t step,
+                                 uint32_t *order_out, uint32_t *n_live_out);
+
+/* Per-kernel launch plan of a context (for timing and tuning):
+ * number of cells handled one wavefront per cell and one workgroup per cell. */
+sdm_status sdm_get_plan(sdm_ctx *ctx, uint32_t *wave_cells, uint32_t *block_cells);
+
+/* Launch-shape knobs; none of them changes any result.
+ *   cells_per_wave : cells each wavefront of the wave-per-cell kernel takes
+ *                    in sequence (1..64);
+ *   waves_per_block: wavefronts per workgroup of that kernel (1, 2, 4, 8);
+ *   block_threads  : threads of the workgroup-per-cell kernel (256 or 1024);
+ *   xcd_remap      : 1 = give each of the 8 XCDs a contiguous range of cells. */
+typedef struct {
+    uint32_t cells_per_wave;
+    uint32_t waves_per_block;
+    uint32_t block_threads;
+    uint32_t xcd_remap;
+} sdm_launch_config;
+sdm_status sdm_get_launch_config(sdm_ctx *ctx, sdm_launch_config *cfg);
+sdm_status sdm_set_launch_config(sdm_ctx *ctx, const sdm_launch_config *cfg);
+
+/* Time every launch configuration of a small candidate set on this context
+ * (each candidate runs `reps` steps), keep the fastest, and restore the state
+ * exactly as it was.  Needs sdm_autotune_workspace_bytes() extra bytes of
+ * device scratch (caller-owned).  best_out (host, nullable) gets the choice. */
+size_t sdm_autotune_workspace_bytes(sdm_ctx *ctx);
+sdm_status sdm_autotune(sdm_ctx *ctx, void *scratch, size_t scratch_bytes, double dt,
+                        sdm_kernel kernel, uint64_t seed, uint32_t reps,
+                        sdm_launch_config *best_out);
+
+/* Release host-side resources.  Device memory stays with the caller. */
+void sdm_destroy(sdm_ctx *ctx);
+
+/* ------------------------------------------------------------------------ */
+/* Batched / served instances: many independent runs advanced by one step    */
+/* call.  Each instance has its own cells, kernel, parameters, dt, seed and  */
+/* step counter; its RNG counters use its own cell indices, so its results   */
+/* are bit-identical alone (sdm_init + sdm_coalesce_step) and in any batch.  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t n_sd;
+    uint32_t n_cells;
+    const uint32_t *cell;     /* dev, instance-local cell index < n_cells */
+    const uint64_t *xi;       /* dev */
+    const double *r;          /* dev */
+    const double *dV;         /* dev, n_cells */
+    sdm_kernel kernel;
+    sdm_kernel_params params;
+    double dt;                /* step length, s */
+    uint64_t seed;
+    uint64_t first_step;      /* step number of the instance's first batch step */
+} sdm_instance_desc;
+
+typedef struct sdm_batch sdm_batch;
+
+/* Device workspace for a batch holding at most max_sd SDs, max_cells cells
+ * and max_instances instances at a time. */
+size_t sdm_batch_workspace_bytes(uint64_t max_sd, uint32_t max_cells, uint32_t max_instances);
+
+/* Create an empty batch over caller-owned workspace (dev, 256-byte aligned). */
+sdm_status sdm_batch_create(sdm_batch **out, void *stream, void *workspace, size_t ws_bytes,
+                            uint64_t max_sd, uint32_t max_cells, uint32_t max_instances);
+
+/* Admit an instance: validate and copy its SDs into the batch (stable sort by
+ * cell, as sdm_init).  Inputs may be freed afterwards.  Synchronises the
+ * stream.  Errors: SDM_EINVAL (bad data), SDM_EBUDGET (not enough free SDs,
+ * cells or instance slots: nothing is changed and the caller may retry after
+ * removing instances). */
+sdm_status sdm_batch_add(sdm_batch *b, const sdm_instance_desc *desc, int32_t *handle_out);
+
+/* Enqueue one step of every admitted instance: instance i uses step number
+ * first_step_i + (number of batch steps since it was admitted).  Returns
+ * without waiting.  use_graph = 1 replays a captured HIP graph of the step
+ * (captured again only after the instance set changed). */
+sdm_status sdm_batch_step(sdm_batch *b, int use_graph);
+
+/* Copy an instance's state in its input order (dev outputs, nullable) and its
+ * counters (host outputs, nullable).  Synchronises the stream. */
+sdm_status sdm_batch_get(sdm_batch *b, int32_t handle, uint64_t *xi_out, double *r_out,
+                         uint64_t *steps_done, uint64_t *pair_tests, uint64_t *collisions);
+
+/* Remove an instance (after copying its state out as sdm_batch_get when the
+ * output pointers are not NULL) and free its SDs, cells and slot. */
+sdm_status sdm_batch_remove(sdm_batch *b, int32_t handle, uint64_t *xi_out, double *r_out);
+
+/* Number of admitted instances, and free capacity. */
+sdm_status sdm_batch_info(sdm_batch *b, uint32_t *n_instances, uint64_t *free_sd,
+                          uint32_t *free_cells);
+
+void sdm_batch_destroy(sdm_batch *b);
+
+/* ------------------------------------------------------------------------ */
+/* Element-wise checks of the device arithmetic (used by the parity tests).  */
+/* All arrays are dev, length n; the call synchronises the stream.           */
+/* ------------------------------------------------------------------------ */
+
+/* out[4i..4i+3] = Philox4x32-10(counter = ctr[4i..4i+3], key = key[2i..2i+1]). */
+sdm_status sdm_debug_philox(void *stream, uint64_t n, const uint32_t *ctr, const uint32_t *key,
+                            uint32_t *out);
+
+/* y[i] = cube root of x[i] rounded to nearest (the rounding the collision
+ * update uses). */
+sdm_status sdm_debug_cbrt(void *stream, uint64_t n, const double *x, double *y);
+
+/* One collision test per element, exactly as inside the step: pair
+ * (xi_a, r_a) first and (xi_b, r_b) second in a cell of n_live live SDs and
+ * volume dV, uniform deviate u.  Outputs: K, p, gamma, and the updated
+ * (xi_a, r_a, xi_b, r_b) written back in place. */
+sdm_status sdm_debug_collide(void *stream, uint64_t n, sdm_kernel kernel,
+                             const sdm_kernel_params *params, double dt,
+                             const uint32_t *n_live, const double *dV, const double *u,
+                             uint64_t *xi_a, double *r_a, uint64_t *xi_b, double *r_b,
+                             double *K_out, double *p_out, uint64_t *gamma_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDM_H_ */

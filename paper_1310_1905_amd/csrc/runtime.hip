@@ -1,0 +1,222 @@
+// runtime.hip -- shared host runtime: errors, scan/sort launches and the
+// dispatch of the step kernels over launch shapes.
+#include "runtime.hpp"
+
+#include <cmath>
+
+namespace sdm {
+
+static thread_local char g_last_error[768] = "";
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+}
+
+bool params_valid(const sdm_kernel_params& p)
+{
+    const double v[7] = {p.golovin_b, p.vt_k1, p.vt_k2, p.vt_k3, p.vt_r1, p.vt_r2, p.efficiency};
+    for (double x : v)
+        if (!std::isfinite(x) || x < 0.0) return false;
+    return p.vt_r1 <= p.vt_r2;
+}
+
+void carve_sort_scratch(Carver& c, uint64_t n_sd, uint32_t n_cells, SortScratch* s)
+{
+    const uint64_t tiles = (n_sd + kRadixTile - 1) / kRadixTile;
+    const uint64_t radix_entries = tiles * kRadixDigits;
+    uint64_t longest = radix_entries > static_cast<uint64_t>(n_cells) + 1 ? radix_entries
+                                                                           : static_cast<uint64_t>(n_cells) + 1;
+    s->keys_a = c.take<uint32_t>(n_sd);
+    s->vals_a = c.take<uint32_t>(n_sd);
+    s->keys_b = c.take<uint32_t>(n_sd);
+    s->vals_b = c.take<uint32_t>(n_sd);
+    s->radix_counts = c.take<uint32_t>(radix_entries);
+    s->tile_sums = c.take<uint32_t>((longest + kScanTile - 1) / kScanTile + 1);
+    s->cell_counts = c.take<uint32_t>(static_cast<uint64_t>(n_cells) + 1);
+}
+
+sdm_status scan_exclusive(hipStream_t s, const uint32_t* in, uint32_t* out, uint64_t n,
+                          uint32_t* tile_sums)
+{
+    if (n == 0) return SDM_OK;
+    const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles > 0xFFFFFFFFull) {
+        set_error("scan of %llu elements is too long", static_cast<unsigned long long>(n));
+        return SDM_EINVAL;
+    }
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(static_cast<uint32_t>(tiles)), dim3(kScanBlock), 0,
+                       s, in, n, tile_sums);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL(k_scan_tile_offsets, dim3(1), dim3(kScanBlock), 0, s, tile_sums,
+                       static_cast<uint32_t>(tiles));
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL(k_scan_tiles, dim3(static_cast<uint32_t>(tiles)), dim3(kScanBlock), 0, s,
+                       in, out, n, tile_sums);
+    SDM_LAUNCHED();
+    return SDM_OK;
+}
+
+sdm_status sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, const double* r,
+                        uint32_t n_cells, const double* dV, SortScratch& scr,
+                        uint32_t* offsets, unsigned int* err_dev, const uint32_t** order)
+{
+    // validation
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(err_dev),
+                       uint64_t(1), 0u);
+    SDM_LAUNCHED();
+    if (n > 0) {
+        hipLaunchKernelGGL(k_validate_sds, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, cell,
+                           r, n_cells, err_dev);
+        SDM_LAUNCHED();
+    }
+    if (n_cells > 0) {
+        hipLaunchKernelGGL(k_validate_volumes, dim3(grid_for(n_cells, 256, 4096)), dim3(256), 0, s,
+                           n_cells, dV, err_dev);
+        SDM_LAUNCHED();
+    }
+    unsigned int err_host = 0;
+    SDM_HIP(hipMemcpyAsync(&err_host, err_dev, sizeof(err_host), hipMemcpyDeviceToHost, s));
+    SDM_HIP(hipStreamSynchronize(s));
+    if (err_host) {
+        set_error("invalid input:%s%s%s", (err_host & kErrCell) ? " cell index >= n_cells" : "",
+                  (err_host & kErrRadius) ? " radius not finite and > 0" : "",
+                  (err_host & kErrVolume) ? " cell volume not finite and > 0" : "");
+        return SDM_EINVAL;
+    }
+
+    // stable LSD radix sort of (cell, input index)
+    uint32_t* ka = scr.keys_a;
+    uint32_t* va = scr.vals_a;
+    uint32_t* kb = scr.keys_b;
+    uint32_t* vb = scr.vals_b;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_keys_iota, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, cell, 0u,
+                           ka, va, 0u);
+        SDM_LAUNCHED();
+        const uint32_t bits = n_cells > 1 ? 32u - static_cast<uint32_t>(__builtin_clz(n_cells - 1u)) : 0u;
+        const uint64_t tiles = (n + kRadixTile - 1) / kRadixTile;
+        for (uint32_t shift = 0; shift < bits; shift += kRadixBits) {
+            hipLaunchKernelGGL(k_radix_count, dim3(static_cast<uint32_t>(tiles)), dim3(kWave), 0, s,
+                               ka, n, shift, scr.radix_counts, static_cast<uint32_t>(tiles));
+            SDM_LAUNCHED();
+            SDM_TRY(scan_exclusive(s, scr.radix_counts, scr.radix_counts, tiles * kRadixDigits,
+                                   scr.tile_sums));
+            hipLaunchKernelGGL(k_radix_scatter, dim3(static_cast<uint32_t>(tiles)), dim3(kWave), 0,
+                               s, ka, va, kb, vb, n, shift, scr.radix_counts,
+                               static_cast<uint32_t>(tiles));
+            SDM_LAUNCHED();
+            uint32_t* t = ka; ka = kb; kb = t;
+            t = va; va = vb; vb = t;
+        }
+    }
+    *order = va;
+
+    // slot offsets = exclusive scan of the per-cell counts
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(uint64_t(n_cells) + 1, 256, 4096)), dim3(256), 0,
+                       s, scr.cell_counts, uint64_t(n_cells) + 1, 0u);
+    SDM_LAUNCHED();
+    if (n > 0) {
+        hipLaunchKernelGGL(k_count_cells, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, cell,
+                           scr.cell_counts);
+        SDM_LAUNCHED();
+    }
+    SDM_TRY(scan_exclusive(s, scr.cell_counts, offsets, uint64_t(n_cells) + 1, scr.tile_sums));
+    return SDM_OK;
+}
+
+// ------------------------------------------------------------ step launch
+template <bool BATCHED, bool PERM>
+static sdm_status launch_wave(hipStream_t s, const StepArgs& a, uint32_t n_items,
+                              const LaunchShape& sh)
+{
+    const uint64_t per_block = static_cast<uint64_t>(sh.cells_per_wave) * sh.waves_per_block;
+    const uint64_t blocks = (n_items + per_block - 1) / per_block;
+    const dim3 grid(static_cast<uint32_t>(blocks));
+    switch (sh.waves_per_block) {
+    case 1: hipLaunchKernelGGL((k_wave_cells<1, BATCHED, PERM>), grid, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_wave_cells<2, BATCHED, PERM>), grid, dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_wave_cells<4, BATCHED, PERM>), grid, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_wave_cells<8, BATCHED, PERM>), grid, dim3(512), 0, s, a); break;
+    default: set_error("waves_per_block must be 1, 2, 4 or 8"); return SDM_EINVAL;
+    }
+    SDM_LAUNCHED();
+    return SDM_OK;
+}
+
+template <bool BATCHED, bool PERM>
+static sdm_status launch_block(hipStream_t s, const StepArgs& a, uint32_t n_items,
+                               const LaunchShape& sh)
+{
+    const uint32_t blocks = n_items < 8192u ? n_items : 8192u;
+    switch (sh.block_threads) {
+    case 256:
+        hipLaunchKernelGGL((k_block_cells<256, BATCHED, PERM>), dim3(blocks), dim3(256), 0, s, a);
+        break;
+    case 1024:
+        hipLaunchKernelGGL((k_block_cells<1024, BATCHED, PERM>), dim3(blocks), dim3(1024), 0, s, a);
+        break;
+    default: set_error("block_threads must be 256 or 1024"); return SDM_EINVAL;
+    }
+    SDM_LAUNCHED();
+    return SDM_OK;
+}
+
+sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* wave_items,
+                       uint32_t n_wave, const uint32_t* block_items, uint32_t n_block,
+                       const LaunchShape& shape, bool batched, bool perm)
+{
+    if (n_wave > 0) {
+        StepArgs a = base;
+        a.items = wave_items;
+        a.n_items = n_wave;
+        a.cells_per_wave = shape.cells_per_wave;
+        a.xcd_remap = shape.xcd_remap;
+        if (batched) SDM_TRY(perm ? launch_wave<true, true>(s, a, n_wave, shape)
+                                  : launch_wave<true, false>(s, a, n_wave, shape));
+        else SDM_TRY(perm ? launch_wave<false, true>(s, a, n_wave, shape)
+                          : launch_wave<false, false>(s, a, n_wave, shape));
+    }
+    if (n_block > 0) {
+        StepArgs a = base;
+        a.items = block_items;
+        a.n_items = n_block;
+        if (batched) SDM_TRY(perm ? launch_block<true, true>(s, a, n_block, shape)
+                                  : launch_block<true, false>(s, a, n_block, shape));
+        else SDM_TRY(perm ? launch_block<false, true>(s, a, n_block, shape)
+                          : launch_block<false, false>(s, a, n_block, shape));
+    }
+    return SDM_OK;
+}
+
+}  // namespace sdm
+
+extern "C" const char* sdm_last_error(void) { return sdm::g_last_error; }
+
+extern "C" const char* sdm_strerror(sdm_status s)
+{
+    switch (s) {
+    case SDM_OK: return "ok";
+    case SDM_EINVAL: return "invalid argument";
+    case SDM_ENOMEM: return "workspace too small";
+    case SDM_EDEVICE: return "HIP runtime error";
+    case SDM_ESTATE: return "invalid state";
+    case SDM_EBUDGET: return "batch capacity exhausted";
+    }
+    return "unknown status";
+}
+
+extern "C" void sdm_default_params(sdm_kernel_params* p)
+{
+    if (!p) return;
+    p->golovin_b = 1500.0;
+    p->vt_k1 = 1.19e8;
+    p->vt_k2 = 8.0e3;
+    p->vt_k3 = 201.0;
+    p->vt_r1 = 40e-6;
+    p->vt_r2 = 600e-6;
+    p->efficiency = 1.0;
+}

@@ -1,0 +1,127 @@
+// runtime.hpp -- host-side helpers shared by the single-run context and the
+// batch: error reporting, workspace carving, launch helpers for the scan and
+// the sort-by-cell used at admission, and the launch of the step kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/sdm.h"
+#include "init_kernels.hpp"
+
+namespace sdm {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+
+#define SDM_HIP(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ::sdm::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
+                             __FILE__, __LINE__);                                       \
+            return SDM_EDEVICE;                                                         \
+        }                                                                               \
+    } while (0)
+
+#define SDM_LAUNCHED()                                                                  \
+    do {                                                                                \
+        hipError_t e_ = hipGetLastError();                                              \
+        if (e_ != hipSuccess) {                                                         \
+            ::sdm::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_),   \
+                             __FILE__, __LINE__);                                       \
+            return SDM_EDEVICE;                                                         \
+        }                                                                               \
+    } while (0)
+
+#define SDM_TRY(...)                                                                    \
+    do {                                                                                \
+        sdm_status s_ = (__VA_ARGS__);                                                         \
+        if (s_ != SDM_OK) return s_;                                                    \
+    } while (0)
+
+// --------------------------------------------------------------- workspace
+struct Carver {
+    uintptr_t base = 0, cur = 0, end = 0;
+    bool measuring = true;
+    explicit Carver(void* ws = nullptr, size_t bytes = 0)
+    {
+        base = cur = reinterpret_cast<uintptr_t>(ws);
+        end = base + bytes;
+        measuring = (ws == nullptr);
+    }
+    template <class T>
+    T* take(uint64_t count)
+    {
+        cur = (cur + 255u) & ~static_cast<uintptr_t>(255u);
+        T* p = reinterpret_cast<T*>(cur);
+        cur += static_cast<uintptr_t>(count * sizeof(T));
+        return p;
+    }
+    size_t used() const { return static_cast<size_t>(cur - base) + 256u; }
+};
+
+inline uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap = 1u << 16)
+{
+    uint64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<uint32_t>(g);
+}
+
+inline KernelParams to_kp(const sdm_kernel_params& p)
+{
+    KernelParams k;
+    k.golovin_b = p.golovin_b;
+    k.k1 = p.vt_k1;
+    k.k2 = p.vt_k2;
+    k.k3 = p.vt_k3;
+    k.r1 = p.vt_r1;
+    k.r2 = p.vt_r2;
+    k.eff = p.efficiency;
+    return k;
+}
+
+bool params_valid(const sdm_kernel_params& p);
+
+// Scratch a sort-by-cell of n SDs needs (bytes), and its launch sequence.
+struct SortScratch {
+    uint32_t* keys_a;
+    uint32_t* vals_a;
+    uint32_t* keys_b;
+    uint32_t* vals_b;
+    uint32_t* radix_counts;   // kRadixDigits * tiles
+    uint32_t* tile_sums;      // scan tile sums
+    uint32_t* cell_counts;    // n_cells + 1
+};
+void carve_sort_scratch(Carver& c, uint64_t n_sd, uint32_t n_cells, SortScratch* s);
+
+// exclusive scan of n uint32 (in may equal out)
+sdm_status scan_exclusive(hipStream_t s, const uint32_t* in, uint32_t* out, uint64_t n,
+                          uint32_t* tile_sums);
+
+// Validate and stable-sort n SDs by cell.  On success: *order (one of the
+// scratch arrays) holds the input index of each storage slot, and
+// offsets[0..n_cells] (dev) the slot offsets.  Synchronises the stream.
+sdm_status sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, const double* r,
+                        uint32_t n_cells, const double* dV, SortScratch& scr,
+                        uint32_t* offsets, unsigned int* err_dev, const uint32_t** order);
+
+// Launch shape of the step kernels.
+struct LaunchShape {
+    uint32_t cells_per_wave = 4;
+    uint32_t waves_per_block = 4;
+    uint32_t block_threads = 256;
+    uint32_t xcd_remap = 1;
+};
+
+// Enqueue the wave-tier and workgroup-tier kernels for one step.
+sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* wave_items,
+                       uint32_t n_wave, const uint32_t* block_items, uint32_t n_block,
+                       const LaunchShape& shape, bool batched, bool perm);
+
+}  // namespace sdm

@@ -1,0 +1,106 @@
+"""Batched instances (sdm_batch_*): every instance's result is bit-identical to
+the oracle and to the same instance run alone, in any mix, with and without the
+captured HIP graph; admission by capacity; removal frees space."""
+import numpy as np
+import pytest
+
+from paper_1310_1905_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_run(oracle_mod, pop, steps, first_step=0):
+    kind = oracle_mod.GOLOVIN if pop.kernel == "golovin" else oracle_mod.GEOMETRIC
+    ref = oracle_mod.SlotState(pop.cell, pop.xi, pop.r, pop.dV)
+    for t in range(first_step, first_step + steps):
+        ref.step(pop.dt, kind, pop.seed, t)
+    return ref
+
+
+def _mixed_instances(n, seed):
+    pops = synth.ensemble(seed=seed, n_instances=n, log2_lo=3, log2_hi=11)
+    # and a few multi-cell columns with ragged cells of both tiers
+    for i in range(3):
+        p = synth.tiny_cells(seed=seed + i, n_cells=20, max_per_cell=500, xi_max=80)
+        p.dV = p.dV * 1e-4
+        p.kernel = "golovin" if i % 2 else "geometric"
+        pops.append(p)
+    return pops
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_matches_oracle_and_alone(sdm_mod, oracle_mod, use_graph):
+    pops = _mixed_instances(24, seed=77)
+    steps = 15
+    b = sdm_mod.Batch(max_sd=sum(p.n_sd for p in pops) + 1000,
+                      max_cells=sum(p.n_cells for p in pops) + 10, max_instances=64)
+    handles = [b.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, p.seed, first_step=5) for p in pops]
+    for _ in range(steps):
+        b.step(use_graph=use_graph)
+    for p, h in zip(pops, handles):
+        xi_b, r_b, cnt = b.get(h)
+        xi_b = xi_b.cpu().numpy().view(np.uint64)
+        r_b = r_b.cpu().numpy()
+        ref = _oracle_run(oracle_mod, p, steps, first_step=5)
+        xi_o, r_o = ref.input_order()
+        assert np.array_equal(xi_b, xi_o), p.name
+        assert np.array_equal(r_b.view(np.uint64), r_o.view(np.uint64)), p.name
+        assert cnt.steps_done == steps
+        assert (cnt.pair_tests, cnt.collisions) == (int(ref.stats[0]), int(ref.stats[1]))
+    # one of them alone, through the single-run context
+    p = pops[-1]
+    ctx = sdm_mod.Context(p.cell, p.xi, p.r, p.dV)
+    for t in range(5, 5 + steps):
+        ctx.step(p.dt, p.kernel, p.seed, t)
+    xi_a, r_a = ctx.state_numpy()
+    xi_b, r_b, _ = b.get(handles[-1])
+    assert np.array_equal(xi_a, xi_b.cpu().numpy().view(np.uint64))
+    assert np.array_equal(r_a.view(np.uint64), r_b.cpu().numpy().view(np.uint64))
+
+
+def test_graph_replays_with_admission_in_between(sdm_mod, oracle_mod):
+    """Instances join and leave between replays; each one's result equals its own
+    oracle run over the steps it was present for."""
+    pops = _mixed_instances(10, seed=5)
+    b = sdm_mod.Batch(max_sd=200000, max_cells=400, max_instances=16)
+    live = {}
+    done = []
+    plan = {0: [0, 1, 2, 3], 3: [4, 5], 6: [6, 7, 8], 9: [9, 10, 11, 12]}
+    leave = {5: [1], 8: [4, 0], 11: [6]}
+    for it in range(14):
+        for i in plan.get(it, []):
+            p = pops[i]
+            live[i] = (b.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, p.seed, first_step=100), it)
+        for i in leave.get(it, []):
+            h, start = live.pop(i)
+            xi, r = b.remove(h)
+            done.append((i, it - start, xi.cpu().numpy().view(np.uint64), r.cpu().numpy()))
+        b.step(use_graph=True)
+    for i, (h, start) in list(live.items()):
+        xi, r = b.remove(h)
+        done.append((i, 14 - start, xi.cpu().numpy().view(np.uint64), r.cpu().numpy()))
+    assert b.info()[0] == 0
+    for i, nsteps, xi, r in done:
+        ref = _oracle_run(oracle_mod, pops[i], nsteps, first_step=100)
+        xi_o, r_o = ref.input_order()
+        assert np.array_equal(xi, xi_o), (i, nsteps)
+        assert np.array_equal(r.view(np.uint64), r_o.view(np.uint64)), (i, nsteps)
+
+
+def test_capacity_is_enforced(sdm_mod):
+    p = synth.box_golovin(seed=1, n_sd=1000)
+    b = sdm_mod.Batch(max_sd=2500, max_cells=8, max_instances=4)
+    h0 = b.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, 1)
+    b.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, 2)
+    with pytest.raises(sdm_mod.SdmError) as e:
+        b.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, 3)
+    assert e.value.status == -5
+    b.remove(h0, with_state=False)
+    b.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, 3)
+    assert b.info()[0] == 2
+    # an invalid instance leaves the batch unchanged
+    q = synth.box_golovin(seed=2, n_sd=100)
+    with pytest.raises(sdm_mod.SdmError) as e:
+        b.add(q.cell, q.xi, -q.r, q.dV, q.kernel, q.dt, 4)
+    assert e.value.status == -1
+    assert b.info() == (2, 500, 6)

@@ -1,0 +1,175 @@
+"""Parity of the HIP coalescence step with the FP64 oracle, through the C ABI.
+
+Bar (spec tolerances): multiplicities and shuffle permutations bit-exact;
+radii within 1e-12 relative -- and since both sides round the cube root
+correctly and evaluate eq. (P_ij) in the same order without contraction, the
+radii are checked bit-exact as well.
+
+Cases: ragged cells of both kernel tiers (wave per cell up to 256 storage slots,
+workgroup per cell above), empty / single-SD / dead-SD cells, both collection
+kernels, many steps; the 2D domain (75 x 75 x 64 SDs, 600 steps); the Golovin box
+(8192 SDs in one cell); the large domain at reduced size in full and at full size
+(1024 x 1024 cells, ~134M SDs, in the launch configuration the benchmark times) on
+sampled cells, which the oracle advances one by one.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1310_1905_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _assert_same(ctx, ref, what):
+    xi_g, r_g = ctx.state_numpy()
+    xi_o, r_o = ref.input_order()
+    bad = np.nonzero(xi_g != xi_o)[0]
+    assert bad.size == 0, f"{what}: {bad.size} multiplicities differ, first at {bad[:5]}"
+    rel = np.abs(r_g - r_o) / r_o
+    assert rel.max() <= 1e-12, f"{what}: radius rel. error {rel.max()}"
+    nbits = int(np.count_nonzero(r_g.view(np.uint64) != r_o.view(np.uint64)))
+    assert nbits == 0, f"{what}: {nbits} radii differ in the last bits"
+    assert ctx.stats() == (int(ref.stats[0]), int(ref.stats[1])), what
+
+
+def _run_pair(sdm_mod, oracle_mod, pop, steps, dt, kernel, dV_scale=1.0, threads=8):
+    kind = oracle_mod.GOLOVIN if kernel == "golovin" else oracle_mod.GEOMETRIC
+    ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV * dV_scale)
+    ref = oracle_mod.SlotState(pop.cell, pop.xi, pop.r, pop.dV * dV_scale)
+    for t in range(steps):
+        ctx.step(dt, kernel, pop.seed, t)
+        ref.step_parallel(dt, kind, pop.seed, t, threads=threads)
+    return ctx, ref
+
+
+@pytest.mark.parametrize("kernel", ["geometric", "golovin"])
+@pytest.mark.parametrize("max_per_cell", [40, 256, 257, 900])
+def test_ragged_cells(sdm_mod, oracle_mod, kernel, max_per_cell):
+    pop = synth.tiny_cells(seed=100 + max_per_cell, n_cells=150, max_per_cell=max_per_cell,
+                           xi_max=60)
+    ctx, ref = _run_pair(sdm_mod, oracle_mod, pop, 12, 3.0, kernel, dV_scale=1e-4)
+    _assert_same(ctx, ref, f"ragged {kernel} {max_per_cell}")
+    assert ref.stats[1] > 0
+
+
+@pytest.mark.parametrize("max_per_cell", [40, 700])
+def test_permutation_bit_exact(sdm_mod, oracle_mod, max_per_cell):
+    pop = synth.tiny_cells(seed=7, n_cells=120, max_per_cell=max_per_cell, dead_fraction=0.3)
+    ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV)
+    ref = oracle_mod.SlotState(pop.cell, pop.xi, pop.r, pop.dV)
+    off = ref.offsets.astype(np.int64)
+    for step in (0, 1, 99, 2 ** 32 - 1):
+        order, nlive = ctx.permutation(seed=31337, step=step)
+        order, nlive = order.cpu().numpy(), nlive.cpu().numpy()
+        for c in range(ref.n_cells):
+            exp = oracle_mod.cell_order(ref.xi[off[c]:off[c + 1]], 31337, c, step)
+            assert nlive[c] == exp.size
+            assert np.array_equal(order[off[c]:off[c] + exp.size], exp), (step, c)
+
+
+def test_empty_and_degenerate_inputs(sdm_mod, oracle_mod):
+    # no SDs at all, a single cell with one SD, and a cell with only dead SDs
+    ctx = sdm_mod.Context(np.zeros(0, np.uint32), np.zeros(0, np.uint64), np.zeros(0),
+                          np.ones(3))
+    ctx.step(1.0, "geometric", 1, 0)
+    assert ctx.stats() == (0, 0)
+    ctx = sdm_mod.Context(np.array([0], np.uint32), np.array([5], np.uint64), np.array([1e-5]),
+                          np.ones(1))
+    ctx.step(1.0, "golovin", 1, 0)
+    xi, r = ctx.state_numpy()
+    assert xi.tolist() == [5] and r.tolist() == [1e-5] and ctx.stats() == (0, 0)
+    ctx = sdm_mod.Context(np.array([0, 0, 1, 1], np.uint32), np.array([0, 0, 3, 4], np.uint64),
+                          np.array([1e-5, 2e-5, 3e-5, 9e-5]), np.array([1e-9, 1e-9]))
+    ctx.step(1.0, "geometric", 1, 0)
+    assert ctx.stats()[0] == 1
+
+
+def test_invalid_inputs_rejected(sdm_mod):
+    with pytest.raises(sdm_mod.SdmError) as e:
+        sdm_mod.Context(np.array([0, 2], np.uint32), np.ones(2, np.uint64), np.ones(2) * 1e-5,
+                        np.ones(2))
+    assert e.value.status == -1
+    with pytest.raises(sdm_mod.SdmError):
+        sdm_mod.Context(np.array([0, 1], np.uint32), np.ones(2, np.uint64),
+                        np.array([1e-5, -1.0]), np.ones(2))
+    with pytest.raises(sdm_mod.SdmError):
+        sdm_mod.Context(np.array([0, 1], np.uint32), np.ones(2, np.uint64),
+                        np.array([1e-5, np.nan]), np.ones(2))
+    with pytest.raises(sdm_mod.SdmError):
+        sdm_mod.Context(np.array([0, 1], np.uint32), np.ones(2, np.uint64), np.ones(2) * 1e-5,
+                        np.array([1.0, 0.0]))
+    ctx = sdm_mod.Context(np.array([0, 1], np.uint32), np.ones(2, np.uint64), np.ones(2) * 1e-5,
+                          np.ones(2))
+    for dt in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(sdm_mod.SdmError):
+            ctx.step(dt, "geometric", 0, 0)
+    with pytest.raises(sdm_mod.SdmError):
+        ctx.step(1.0, 7, 0, 0)
+    with pytest.raises(sdm_mod.SdmError):
+        ctx.step(1.0, "geometric", 0, 2 ** 32)
+
+
+def test_domain_2d_full_run(sdm_mod, oracle_mod):
+    pop = synth.domain_2d(seed=synth.SEEDS[1])
+    ctx, ref = _run_pair(sdm_mod, oracle_mod, pop, pop.steps, pop.dt, pop.kernel, threads=16)
+    _assert_same(ctx, ref, "domain_2d 600 steps")
+
+
+def test_box_golovin(sdm_mod, oracle_mod):
+    pop = synth.box_golovin(seed=synth.SEEDS[2])
+    ctx, ref = _run_pair(sdm_mod, oracle_mod, pop, 400, pop.dt, pop.kernel, threads=1)
+    _assert_same(ctx, ref, "box golovin 400 steps")
+    assert ctx.plan() == (0, 1)
+
+
+def test_large_domain_reduced_full_parity(sdm_mod, oracle_mod):
+    pop = synth.large_domain(seed=synth.SEEDS[3], nx=128, ny=128, shuffle=True)
+    ctx, ref = _run_pair(sdm_mod, oracle_mod, pop, 6, pop.dt, pop.kernel, threads=16)
+    _assert_same(ctx, ref, "large domain 128x128")
+
+
+def test_large_domain_full_size_sampled_cells(sdm_mod, oracle_mod):
+    """1024 x 1024 cells (~134M SDs) in the benchmark's launch configuration; the
+    oracle advances 2048 sampled cells (plus every injected empty/single cell kind)
+    one by one with their own RNG cell index."""
+    pop = synth.large_domain(seed=synth.SEEDS[0])
+    ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV)
+    cnt = np.bincount(pop.cell, minlength=pop.n_cells)
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    g = np.random.default_rng(5)
+    sample = np.unique(np.concatenate([g.choice(pop.n_cells, 2048, replace=False),
+                                       [0, 1, 997, 992, pop.n_cells - 1]]))
+    steps = 3
+    refs = {}
+    for c in sample:
+        sl = slice(off[c], off[c + 1])
+        refs[c] = [pop.xi[sl].copy(), pop.r[sl].copy()]
+    params = np.array(oracle_mod.DEFAULT_PARAMS, dtype=np.float64)
+    stats = np.zeros(2, np.uint64)
+    for t in range(steps):
+        ctx.step(pop.dt, pop.kernel, pop.seed, t)
+        for c in sample:
+            xi_c, r_c = refs[c]
+            offs = np.array([0, xi_c.size], np.uint64)
+            dv = np.ascontiguousarray(pop.dV[c:c + 1])
+            oracle_mod.lib().oracle_step(1, offs.ctypes.data, dv.ctypes.data, xi_c.ctypes.data,
+                                         r_c.ctypes.data, pop.dt, oracle_mod.GEOMETRIC,
+                                         params.ctypes.data, pop.seed, t, int(c),
+                                         stats.ctypes.data)
+    xi_g, r_g = ctx.state_numpy()          # input order == storage order (cell-major input)
+    for c in sample:
+        sl = slice(off[c], off[c + 1])
+        assert np.array_equal(xi_g[sl], refs[c][0]), c
+        assert np.array_equal(r_g[sl].view(np.uint64), refs[c][1].view(np.uint64)), c
+    # every cell: droplet volume conserved, number non-increasing
+    torch.cuda.empty_cache()
+    v0 = np.bincount(pop.cell, weights=pop.xi.astype(np.float64) * pop.r ** 3,
+                     minlength=pop.n_cells)
+    v1 = np.bincount(pop.cell, weights=xi_g.astype(np.float64) * r_g ** 3, minlength=pop.n_cells)
+    nz = v0 > 0
+    assert np.all(np.abs(v1[nz] - v0[nz]) <= 1e-12 * v0[nz])
+    pairs, coll = ctx.stats()
+    live = cnt[cnt > 0]
+    assert pairs >= steps * int((live // 2).sum()) * 0.999
+    assert coll > 0
