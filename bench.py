@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the super-droplet coalescence step on one MI355X.
+
+Default workload: the large domain -- 1024 x 1024 cells, Poisson(128) super-droplets
+per cell (~134M SDs, injected empty and single-SD cells), bimodal lognormal radii,
+geometric kernel, dt = 0.5 s -- with its state resident in HBM.  A step is one
+coalescence step of every cell (sdm_coalesce_step: live count, shuffle, pairing,
+collision update, all in one kernel launch for this cell-size range).
+
+Prints ONE JSON line: pair tests/s over the timed steps, the roofline of the
+dominant kernel (algorithmic bytes per launch / mean launch duration from HIP events
+on the launch stream), and the FP64 CPU oracle timed on a bounded sample.
+
+Other workloads (--workload): domain2d, box, ensemble (batched vs per-instance plain
+launches), served (continuous batching vs sequential plain launches).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coalescence pair tests/s + achieved HBM GB/s; served p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes: read xi and r of every SD (16 B), offset (4 B) and volume (8 B)
+# of every cell, write the multiplicity of j and the radius of k per collision (16 B)
+BYTES_PER_SD = 16
+BYTES_PER_CELL = 12
+BYTES_PER_COLLISION = 16
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_wave_groups_large_domain.txt")
+KERNEL_SOURCES = ["paper_1310_1905_amd/csrc/step_kernels.hpp",
+                  "paper_1310_1905_amd/csrc/device_math.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pop, n_cells_sample: int, steps: int):
+    """The FP64 oracle on the first n_cells_sample cells for `steps` steps,
+    threads over independent cell ranges."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    ncs = min(n_cells_sample, pop.n_cells)
+    n_sd = int(np.count_nonzero(pop.cell < ncs))
+    st = oracle.SlotState(pop.cell[:n_sd], pop.xi[:n_sd], pop.r[:n_sd], pop.dV[:ncs])
+    kind = oracle.GEOMETRIC if pop.kernel == "geometric" else oracle.GOLOVIN
+    t0 = time.perf_counter()
+    for t in range(steps):
+        st.step_parallel(pop.dt, kind, pop.seed, t, threads=threads)
+    el = time.perf_counter() - t0
+    return {"value": float(st.stats[0]) / el, "unit": "pair tests/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {ncs} of {pop.n_cells} cells ({n_sd} SDs), {steps} steps, "
+                      f"{el:.1f} s wall on {threads} threads"}
+
+
+def bench_large(args):
+    import torch
+
+    from paper_1310_1905_amd import sdm, synth
+    log("generating the 1024x1024-cell population")
+    pop = synth.large_domain(seed=synth.SEEDS[0], nx=args.nx, ny=args.nx)
+    log(f"{pop.n_sd} SDs in {pop.n_cells} cells; initialising")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    ctx = sdm.Context(pop.cell, pop.xi, pop.r, pop.dV, stream=stream)
+    plan = ctx.plan()
+    if args.launch:
+        slots, gpw, wpb, bt, xr = (int(v) for v in args.launch.split(","))
+        ctx.set_launch_config(group_slots=slots, groups_per_wave=gpw, waves_per_block=wpb,
+                              block_threads=bt, xcd_remap=xr)
+    elif args.autotune:
+        best = ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=3)
+        log(f"autotuned launch config {best.as_dict()}")
+    cfg = ctx.launch_config().as_dict()
+    for t in range(args.warmup):
+        ctx.step(pop.dt, pop.kernel, pop.seed, t)
+    torch.cuda.synchronize()
+    p0, c0 = ctx.stats()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record(stream)
+        ctx.step(pop.dt, pop.kernel, pop.seed, args.warmup + i)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    p1, c1 = ctx.stats()
+    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    pairs = p1 - p0
+    colls = c1 - c0
+    log(f"{args.steps} steps in {wall * 1e3:.2f} ms; mean launch {launch_ms * 1e3:.1f} us; "
+        f"{pairs} pair tests, {colls} collisions")
+    alg_bytes = (BYTES_PER_SD * pop.n_sd + BYTES_PER_CELL * pop.n_cells
+                 + BYTES_PER_COLLISION * colls / args.steps)
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": pairs / wall, "unit": "pair tests/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "large_domain_1024x1024_poisson128_geometric_dt0.5",
+                   "n_sd": pop.n_sd, "n_cells": pop.n_cells, "parallelism": "single_gpu",
+                   "groups": plan[0], "wave_cells": plan[1], "block_cells": plan[2],
+                   "launch": cfg},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "k_wave_groups", "algorithmic_bytes_per_launch": alg_bytes,
+                     "mean_launch_ms": launch_ms},
+    }
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    if args.calib_copy_gib > 0:
+        # plain copy of known size, for scaling the HBM byte counters of a profile run
+        n = int(args.calib_copy_gib * (1 << 30)) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 8 * n
+        del a, b
+    if args.cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(pop, args.cpu_cells, args.cpu_steps)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "domain2d", "box", "ensemble", "served"])
+    ap.add_argument("--nx", type=int, default=1024, help="cells per side (large domain)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false")
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--cpu-cells", type=int, default=1 << 20)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0)
+    ap.add_argument("--instances", type=int, default=4096, help="ensemble size")
+    ap.add_argument("--requests", type=int, default=48, help="served stream length")
+    ap.add_argument("--max-run", type=int, default=3600, help="longest served run (steps)")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="served HBM budget")
+    ap.add_argument("--launch", default="",
+                    help="fixed launch config group_slots,groups_per_wave,waves_per_block,"
+                         "block_threads,xcd_remap (skips the autotuner)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the coalescence step "
+                                   "shards by cells with no exchange (see DESIGN.md), but no "
+                                   "multi-GPU path is provided", "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.workload == "large":
+        out = bench_large(args)
+    else:
+        from paper_1310_1905_amd import bench_workloads
+        out = bench_workloads.run(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -148,18 +148,23 @@ sdm_status sdm_get_layout(sdm_ctx *ctx, const uint32_t **offsets, const uint32_t
 sdm_status sdm_debug_permutation(sdm_ctx *ctx, uint64_t seed, uint64_t step,
                                  uint32_t *order_out, uint32_t *n_live_out);
 
-/* Per-kernel launch plan of a context (for timing and tuning):
- * number of cells handled one wavefront per cell and one workgroup per cell. */
-sdm_status sdm_get_plan(sdm_ctx *ctx, uint32_t *wave_cells, uint32_t *block_cells);
+/* Launch plan of a context: number of wave-tier groups (runs of consecutive
+ * cells processed by one wavefront), cells in them, and cells handled one
+ * workgroup per cell (cells with more storage slots than a group holds).
+ * host outputs, nullable. */
+sdm_status sdm_get_plan(sdm_ctx *ctx, uint32_t *groups, uint32_t *wave_cells,
+                        uint32_t *block_cells);
 
 /* Launch-shape knobs; none of them changes any result.
- *   cells_per_wave : cells each wavefront of the wave-per-cell kernel takes
- *                    in sequence (1..64);
- *   waves_per_block: wavefronts per workgroup of that kernel (1, 2, 4, 8);
+ *   group_slots    : storage slots one wavefront handles per group (256 or
+ *                    512); cells with more slots go to the workgroup tier;
+ *   groups_per_wave: groups each wavefront takes in sequence (1..64);
+ *   waves_per_block: wavefronts per workgroup of the wave tier (1, 2, 4);
  *   block_threads  : threads of the workgroup-per-cell kernel (256 or 1024);
- *   xcd_remap      : 1 = give each of the 8 XCDs a contiguous range of cells. */
+ *   xcd_remap      : 1 = give each of the 8 XCDs a contiguous range of groups. */
 typedef struct {
-    uint32_t cells_per_wave;
+    uint32_t group_slots;
+    uint32_t groups_per_wave;
     uint32_t waves_per_block;
     uint32_t block_threads;
     uint32_t xcd_remap;

@@ -1,0 +1,149 @@
+"""Secondary benchmark workloads of bench.py (one JSON line each):
+
+  domain2d -- 75 x 75 cells x 64 SDs, geometric kernel, dt = 1 s (latency-bound: us/step)
+  box      -- one cell of 2^13 SDs, Golovin kernel, dt = 1 s (latency-bound: us/step)
+  ensemble -- 4096 independent single-cell boxes (N_sd log-uniform 2^8..2^16), one
+              graph-replayed batch step vs per-instance plain launches
+  served   -- Poisson request stream served by continuous batching vs one request at a
+              time with plain launches; p50/p99 latency
+"""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import sdm, serve, synth
+
+METRIC = "coalescence pair tests/s + achieved HBM GB/s; served p50/p99 latency"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _line(args, value, ms_per_step, workload, extra=None, unit="pair tests/s"):
+    out = {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": workload, "parallelism": "single_gpu"}}
+    if extra:
+        out["config"].update(extra)
+    return out
+
+
+def _single(args, pop, workload):
+    stream = torch.cuda.Stream()
+    ctx = sdm.Context(pop.cell, pop.xi, pop.r, pop.dV, stream=stream)
+    for t in range(args.warmup):
+        ctx.step(pop.dt, pop.kernel, pop.seed, t)
+    torch.cuda.synchronize()
+    p0, _ = ctx.stats()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.step(pop.dt, pop.kernel, pop.seed, args.warmup + i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    p1, _ = ctx.stats()
+    return _line(args, (p1 - p0) / wall, wall * 1e3 / args.steps, workload,
+                 {"n_sd": pop.n_sd, "n_cells": pop.n_cells, "us_per_step": wall * 1e6 / args.steps})
+
+
+def run_ensemble(args):
+    pops = synth.ensemble(seed=synth.SEEDS[0], n_instances=args.instances)
+    n_sd = sum(p.n_sd for p in pops)
+    log(f"ensemble: {len(pops)} instances, {n_sd} SDs")
+    b = sdm.Batch(n_sd, len(pops), len(pops))
+    handles = [b.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, p.seed) for p in pops]
+    for _ in range(args.warmup):
+        b.step(use_graph=True)
+    torch.cuda.synchronize()
+    pt0 = sum(b.get(h, with_state=False)[2].pair_tests for h in handles)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.step(use_graph=True)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    pt1 = sum(b.get(h, with_state=False)[2].pair_tests for h in handles)
+    batched = (pt1 - pt0) / wall_b
+    # plain launches: one context per instance, one launch per instance and step
+    plain_steps = max(2, args.steps // 20)
+    stream = torch.cuda.Stream()
+    ctxs = [sdm.Context(p.cell, p.xi, p.r, p.dV, stream=stream) for p in pops]
+    for c, p in zip(ctxs, pops):
+        c.step(p.dt, p.kernel, p.seed, 0)
+    torch.cuda.synchronize()
+    q0 = sum(c.stats()[0] for c in ctxs)
+    t0 = time.perf_counter()
+    for t in range(plain_steps):
+        for c, p in zip(ctxs, pops):
+            c.step(p.dt, p.kernel, p.seed, 1 + t)
+    torch.cuda.synchronize()
+    wall_p = time.perf_counter() - t0
+    q1 = sum(c.stats()[0] for c in ctxs)
+    plain = (q1 - q0) / wall_p
+    # equal accuracy: the same instance is bit-identical in both modes
+    same = True
+    for k in range(0, len(pops), max(1, len(pops) // 16)):
+        ref = sdm.Context(pops[k].cell, pops[k].xi, pops[k].r, pops[k].dV, stream=stream)
+        for t in range(args.warmup + args.steps):
+            ref.step(pops[k].dt, pops[k].kernel, pops[k].seed, t)
+        xa, ra = ref.state_numpy()
+        xb, rb, _ = b.get(handles[k])
+        same &= bool(np.array_equal(xa, xb.cpu().numpy().view(np.uint64)) and
+                     np.array_equal(ra.view(np.uint64), rb.cpu().numpy().view(np.uint64)))
+        ref.close()
+    return _line(args, batched, wall_b * 1e3 / args.steps, "ensemble_4096_boxes_batched_graph",
+                 {"n_sd": n_sd, "instances": len(pops),
+                  "plain_launch_pair_tests_per_s": plain,
+                  "plain_ms_per_step": wall_p * 1e3 / plain_steps,
+                  "speedup_vs_plain": batched / plain, "bit_identical_to_plain": same})
+
+
+def run_served(args):
+    reqs = synth.request_stream(seed=synth.SEEDS[0], n_requests=args.requests, rate=1.0,
+                                steps_hi=args.max_run)
+    total_steps_sd = sum(q.pop.n_sd * q.pop.steps for q in reqs)
+    log(f"served: {len(reqs)} requests, {total_steps_sd:.3g} SD-steps")
+    # saturated throughput: everything arrives at once
+    eng = serve.Engine(budget_bytes=int(args.budget_gib * (1 << 30)))
+    t0 = time.perf_counter()
+    res_sat = eng.run(reqs, time_scale=0.0)
+    sat_wall = time.perf_counter() - t0
+    eng.close()
+    sat_rate = len(reqs) / sat_wall
+    # Poisson arrivals at 0.7x the saturated request rate
+    scale = 1.0 / (0.7 * sat_rate)
+    eng = serve.Engine(budget_bytes=int(args.budget_gib * (1 << 30)))
+    t0 = time.perf_counter()
+    res = eng.run(reqs, time_scale=scale)
+    wall = time.perf_counter() - t0
+    eng.close()
+    pairs = sum(r.pair_tests for r in res)
+    served = serve.latency_summary(res)
+    t0 = time.perf_counter()
+    seq = serve.run_sequential(reqs, time_scale=scale)
+    wall_seq = time.perf_counter() - t0
+    seq_pairs = sum(r.pair_tests for r in seq)
+    return _line(args, pairs / wall, None, "served_poisson_stream_continuous_batching",
+                 {"requests": len(reqs), "arrival_rate_per_s": 1.0 / scale,
+                  "saturated_requests_per_s": sat_rate,
+                  "latency": served, "sequential_latency": serve.latency_summary(seq),
+                  "sequential_pair_tests_per_s": seq_pairs / wall_seq,
+                  "speedup_vs_sequential": (pairs / wall) / (seq_pairs / wall_seq),
+                  "saturated_pair_tests_per_s": sum(r.pair_tests for r in res_sat) / sat_wall})
+
+
+def run(args):
+    torch.cuda.set_device(0)
+    if args.workload == "domain2d":
+        return _single(args, synth.domain_2d(seed=synth.SEEDS[0]), "domain_2d_75x75x64_geometric")
+    if args.workload == "box":
+        return _single(args, synth.box_golovin(seed=synth.SEEDS[0]), "box_8192_golovin")
+    if args.workload == "ensemble":
+        return run_ensemble(args)
+    if args.workload == "served":
+        return run_served(args)
+    raise ValueError(args.workload)

@@ -104,7 +104,8 @@ struct BatchLayout {
     uint32_t* cell_inst;
     uint32_t* cell_local;
     InstanceRec* inst;
-    uint32_t* wave_items;
+    uint32_t* group_begin;
+    uint32_t* group_end;
     uint32_t* block_items;
     unsigned int* err;
     uint32_t* local_off;     // admission: offsets of the instance being added
@@ -130,7 +131,8 @@ BatchLayout batch_layout(void* ws, size_t bytes, uint64_t max_sd, uint32_t max_c
     L.cell_inst = cv.take<uint32_t>(max_cells);
     L.cell_local = cv.take<uint32_t>(max_cells);
     L.inst = cv.take<InstanceRec>(max_inst);
-    L.wave_items = cv.take<uint32_t>(max_cells);
+    L.group_begin = cv.take<uint32_t>(max_cells);
+    L.group_end = cv.take<uint32_t>(max_cells);
     L.block_items = cv.take<uint32_t>(max_cells);
     L.err = cv.take<unsigned int>(64);
     L.local_off = cv.take<uint32_t>(uint64_t(max_cells) + 1);
@@ -158,7 +160,7 @@ struct sdm_batch {
     BatchLayout L{};
     RangePool sd_pool, cell_pool;
     std::vector<HostInstance> inst;
-    uint32_t n_wave = 0, n_block = 0;
+    uint32_t n_groups = 0, n_block = 0;
     bool dirty = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -167,31 +169,27 @@ struct sdm_batch {
 
 static sdm_status rebuild_lists(sdm_batch* b)
 {
-    std::vector<uint32_t> wave;
-    std::vector<std::pair<uint32_t, uint32_t>> block;   // (size, cell)
+    // groups never span two instances: each instance's cells are planned on their own
+    Plan plan;
     for (const HostInstance& h : b->inst) {
-        if (!h.live) continue;
-        for (uint32_t c = 0; c < h.n_cells; ++c) {
-            const uint32_t cid = static_cast<uint32_t>(h.cell_begin + c);
-            const uint32_t sz = h.cell_sizes[c];
-            if (sz < 2) continue;                    // never a pair
-            if (sz <= static_cast<uint32_t>(kWaveMaxSlots)) wave.push_back(cid);
-            else block.emplace_back(sz, cid);
-        }
+        if (!h.live || h.n_cells == 0) continue;
+        plan_cells(plan, static_cast<uint32_t>(h.cell_begin), h.cell_sizes.data(), h.n_cells,
+                   b->shape.group_slots);
     }
-    std::stable_sort(block.begin(), block.end(),
-                     [](const auto& x, const auto& y) { return x.first > y.first; });
-    std::vector<uint32_t> bl(block.size());
-    for (size_t i = 0; i < block.size(); ++i) bl[i] = block[i].second;
-    if (!wave.empty())
-        SDM_HIP(hipMemcpyAsync(b->L.wave_items, wave.data(), wave.size() * 4, hipMemcpyHostToDevice,
+    plan_finish(plan);
+    const size_t ng = plan.group_begin.size();
+    if (ng) {
+        SDM_HIP(hipMemcpyAsync(b->L.group_begin, plan.group_begin.data(), ng * 4,
+                               hipMemcpyHostToDevice, b->stream));
+        SDM_HIP(hipMemcpyAsync(b->L.group_end, plan.group_end.data(), ng * 4, hipMemcpyHostToDevice,
                                b->stream));
-    if (!bl.empty())
-        SDM_HIP(hipMemcpyAsync(b->L.block_items, bl.data(), bl.size() * 4, hipMemcpyHostToDevice,
-                               b->stream));
+    }
+    if (!plan.block_cells.empty())
+        SDM_HIP(hipMemcpyAsync(b->L.block_items, plan.block_cells.data(),
+                               plan.block_cells.size() * 4, hipMemcpyHostToDevice, b->stream));
     SDM_HIP(hipStreamSynchronize(b->stream));
-    b->n_wave = static_cast<uint32_t>(wave.size());
-    b->n_block = static_cast<uint32_t>(bl.size());
+    b->n_groups = static_cast<uint32_t>(ng);
+    b->n_block = static_cast<uint32_t>(plan.block_cells.size());
     b->dirty = true;
     return SDM_OK;
 }
@@ -201,6 +199,7 @@ static sdm_status enqueue_step(sdm_batch* b)
     StepArgs a{};
     a.xi = b->L.xi;
     a.r = b->L.r;
+    a.n_sd = b->max_sd;
     a.off_begin = b->L.cell_off;
     a.off_end = b->L.cell_end;
     a.dV = b->L.dV;
@@ -211,8 +210,8 @@ static sdm_status enqueue_step(sdm_batch* b)
     a.scr_tmp = b->L.scr_tmp;
     a.scr_pos = b->L.scr_pos;
     a.scr_cnt = b->L.scr_cnt;
-    SDM_TRY(launch_step(b->stream, a, b->L.wave_items, b->n_wave, b->L.block_items, b->n_block,
-                        b->shape, true, false));
+    SDM_TRY(launch_step(b->stream, a, b->L.group_begin, b->L.group_end, b->n_groups,
+                        b->L.block_items, b->n_block, b->shape, true, false));
     hipLaunchKernelGGL(k_advance_instances, dim3(grid_for(b->max_inst, 256, 1024)), dim3(256), 0,
                        b->stream, b->L.inst, b->max_inst);
     SDM_LAUNCHED();

@@ -1,9 +1,8 @@
 // context.hip -- the single-run C ABI: sdm_init / sdm_coalesce_step and the
-// state, counter, layout and permutation queries of a context.
+// state, counter, layout, plan and permutation queries of a context.
 #include "runtime.hpp"
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 
 using namespace sdm;
@@ -19,7 +18,8 @@ struct sdm_ctx {
     uint32_t* id = nullptr;
     uint32_t* offsets = nullptr;
     double* dV = nullptr;
-    uint32_t* wave_items = nullptr;
+    uint32_t* group_begin = nullptr;
+    uint32_t* group_end = nullptr;
     uint32_t* block_items = nullptr;
     unsigned long long* stats = nullptr;
     unsigned int* err = nullptr;
@@ -28,8 +28,8 @@ struct sdm_ctx {
     uint32_t* scr_pos = nullptr;
     uint32_t* scr_cnt = nullptr;
     // plan
-    uint32_t n_wave = 0, n_block = 0;
-    bool wave_identity = false;
+    std::vector<uint32_t> sizes;   // storage slots per cell (host copy)
+    uint32_t n_groups = 0, n_wave_cells = 0, n_block = 0;
     LaunchShape shape;
 };
 
@@ -41,11 +41,12 @@ struct CtxLayout {
     uint32_t* id;
     uint32_t* offsets;
     double* dV;
-    uint32_t* wave_items;
+    uint32_t* group_begin;
+    uint32_t* group_end;
     uint32_t* block_items;
     unsigned long long* stats;
     unsigned int* err;
-    // scratch (block-tier sort arrays during steps; sort-by-cell arrays during init)
+    // scratch (workgroup-tier sort arrays during steps; sort-by-cell arrays during init)
     uint64_t* scr_kv;
     uint64_t* scr_tmp;
     uint32_t* scr_pos;
@@ -63,7 +64,8 @@ CtxLayout layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t c)
     L.id = cv.take<uint32_t>(n);
     L.offsets = cv.take<uint32_t>(uint64_t(c) + 1);
     L.dV = cv.take<double>(c);
-    L.wave_items = cv.take<uint32_t>(c);
+    L.group_begin = cv.take<uint32_t>(c);
+    L.group_end = cv.take<uint32_t>(c);
     L.block_items = cv.take<uint32_t>(c);
     L.stats = cv.take<unsigned long long>(uint64_t(kStatSlots) * kStatStride);
     L.err = cv.take<unsigned int>(64);
@@ -86,6 +88,7 @@ StepArgs base_args(const sdm_ctx* x)
     StepArgs a{};
     a.xi = x->xi;
     a.r = x->r;
+    a.n_sd = x->n_sd;
     a.off_begin = x->offsets;
     a.off_end = x->offsets + 1;
     a.dV = x->dV;
@@ -104,6 +107,29 @@ sdm_status check_ctx(const sdm_ctx* x)
         set_error("context is NULL");
         return SDM_EINVAL;
     }
+    return SDM_OK;
+}
+
+// Build the work lists for the current launch shape and upload them.
+sdm_status upload_plan(sdm_ctx* x)
+{
+    Plan plan;
+    plan_cells(plan, 0, x->sizes.data(), x->n_cells, x->shape.group_slots);
+    plan_finish(plan);
+    const size_t ng = plan.group_begin.size();
+    if (ng) {
+        SDM_HIP(hipMemcpyAsync(x->group_begin, plan.group_begin.data(), ng * 4,
+                               hipMemcpyHostToDevice, x->stream));
+        SDM_HIP(hipMemcpyAsync(x->group_end, plan.group_end.data(), ng * 4, hipMemcpyHostToDevice,
+                               x->stream));
+    }
+    if (!plan.block_cells.empty())
+        SDM_HIP(hipMemcpyAsync(x->block_items, plan.block_cells.data(), plan.block_cells.size() * 4,
+                               hipMemcpyHostToDevice, x->stream));
+    SDM_HIP(hipStreamSynchronize(x->stream));
+    x->n_groups = static_cast<uint32_t>(ng);
+    x->n_wave_cells = plan.wave_cells;
+    x->n_block = static_cast<uint32_t>(plan.block_cells.size());
     return SDM_OK;
 }
 
@@ -169,22 +195,11 @@ extern "C" sdm_status sdm_init(sdm_ctx** out, void* stream, void* workspace, siz
                        uint64_t(kStatSlots) * kStatStride, 0ull);
     SDM_LAUNCHED();
 
-    // plan: cells up to kWaveMaxSlots slots go to the wave tier, larger ones
-    // to the workgroup tier
     std::vector<uint32_t> off(uint64_t(n_cells) + 1);
     SDM_HIP(hipMemcpyAsync(off.data(), L.offsets, off.size() * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, s));
     SDM_HIP(hipStreamSynchronize(s));
-    std::vector<uint32_t> wave, block;
-    for (uint32_t c = 0; c < n_cells; ++c) {
-        const uint32_t cnt = off[c + 1] - off[c];
-        if (cnt <= static_cast<uint32_t>(kWaveMaxSlots)) wave.push_back(c);
-        else block.push_back(c);
-    }
-    // larger cells first
-    std::stable_sort(block.begin(), block.end(), [&](uint32_t a, uint32_t b) {
-        return off[a + 1] - off[a] > off[b + 1] - off[b];
-    });
+
     auto* x = new sdm_ctx();
     x->stream = s;
     x->n_sd = n_sd;
@@ -195,7 +210,8 @@ extern "C" sdm_status sdm_init(sdm_ctx** out, void* stream, void* workspace, siz
     x->id = L.id;
     x->offsets = L.offsets;
     x->dV = L.dV;
-    x->wave_items = L.wave_items;
+    x->group_begin = L.group_begin;
+    x->group_end = L.group_end;
     x->block_items = L.block_items;
     x->stats = L.stats;
     x->err = L.err;
@@ -203,32 +219,12 @@ extern "C" sdm_status sdm_init(sdm_ctx** out, void* stream, void* workspace, siz
     x->scr_tmp = L.scr_tmp;
     x->scr_pos = L.scr_pos;
     x->scr_cnt = L.scr_cnt;
-    x->n_wave = static_cast<uint32_t>(wave.size());
-    x->n_block = static_cast<uint32_t>(block.size());
-    x->wave_identity = (wave.size() == n_cells);
-    if (!x->wave_identity && !wave.empty()) {
-        hipError_t e = hipMemcpyAsync(L.wave_items, wave.data(), wave.size() * sizeof(uint32_t),
-                                      hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) {
-            delete x;
-            set_error("hipMemcpyAsync: %s", hipGetErrorString(e));
-            return SDM_EDEVICE;
-        }
-    }
-    if (!block.empty()) {
-        hipError_t e = hipMemcpyAsync(L.block_items, block.data(), block.size() * sizeof(uint32_t),
-                                      hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) {
-            delete x;
-            set_error("hipMemcpyAsync: %s", hipGetErrorString(e));
-            return SDM_EDEVICE;
-        }
-    }
-    hipError_t e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
+    x->sizes.resize(n_cells);
+    for (uint32_t c = 0; c < n_cells; ++c) x->sizes[c] = off[c + 1] - off[c];
+    const sdm_status st = upload_plan(x);
+    if (st != SDM_OK) {
         delete x;
-        set_error("hipStreamSynchronize: %s", hipGetErrorString(e));
-        return SDM_EDEVICE;
+        return st;
     }
     *out = x;
     return SDM_OK;
@@ -257,14 +253,19 @@ static sdm_status step_args(sdm_ctx* x, double dt, sdm_kernel kernel, uint64_t s
     return SDM_OK;
 }
 
+static sdm_status launch(sdm_ctx* x, const StepArgs& a, bool perm)
+{
+    return launch_step(x->stream, a, x->group_begin, x->group_end, x->n_groups, x->block_items,
+                       x->n_block, x->shape, false, perm);
+}
+
 extern "C" sdm_status sdm_coalesce_step(sdm_ctx* x, double dt, sdm_kernel kernel, uint64_t seed,
                                         uint64_t step)
 {
     SDM_TRY(check_ctx(x));
     StepArgs a;
     SDM_TRY(step_args(x, dt, kernel, seed, step, &a));
-    return launch_step(x->stream, a, x->wave_identity ? nullptr : x->wave_items, x->n_wave,
-                       x->block_items, x->n_block, x->shape, false, false);
+    return launch(x, a, false);
 }
 
 extern "C" sdm_status sdm_debug_permutation(sdm_ctx* x, uint64_t seed, uint64_t step,
@@ -279,8 +280,7 @@ extern "C" sdm_status sdm_debug_permutation(sdm_ctx* x, uint64_t seed, uint64_t 
     SDM_TRY(step_args(x, 1.0, SDM_KERNEL_GOLOVIN, seed, step, &a));
     a.perm_out = order_out;
     a.nlive_out = n_live_out;
-    SDM_TRY(launch_step(x->stream, a, x->wave_identity ? nullptr : x->wave_items, x->n_wave,
-                        x->block_items, x->n_block, x->shape, false, true));
+    SDM_TRY(launch(x, a, true));
     SDM_HIP(hipStreamSynchronize(x->stream));
     return SDM_OK;
 }
@@ -323,21 +323,41 @@ extern "C" sdm_status sdm_get_layout(sdm_ctx* x, const uint32_t** offsets,
     return SDM_OK;
 }
 
-extern "C" sdm_status sdm_get_plan(sdm_ctx* x, uint32_t* wave_cells, uint32_t* block_cells)
+extern "C" sdm_status sdm_get_plan(sdm_ctx* x, uint32_t* groups, uint32_t* wave_cells,
+                                   uint32_t* block_cells)
 {
     SDM_TRY(check_ctx(x));
-    if (wave_cells) *wave_cells = x->n_wave;
+    if (groups) *groups = x->n_groups;
+    if (wave_cells) *wave_cells = x->n_wave_cells;
     if (block_cells) *block_cells = x->n_block;
     return SDM_OK;
 }
 
-static bool shape_valid(const sdm_launch_config& c)
+static LaunchShape from_cfg(const sdm_launch_config& c)
 {
-    const bool waves_ok = c.waves_per_block == 1 || c.waves_per_block == 2 ||
-                          c.waves_per_block == 4 || c.waves_per_block == 8;
-    const bool block_ok = c.block_threads == 256 || c.block_threads == 1024;
-    return waves_ok && block_ok && c.cells_per_wave >= 1 && c.cells_per_wave <= 64 &&
-           c.xcd_remap <= 1;
+    LaunchShape s;
+    s.group_slots = c.group_slots;
+    s.groups_per_wave = c.groups_per_wave;
+    s.waves_per_block = c.waves_per_block;
+    s.block_threads = c.block_threads;
+    s.xcd_remap = c.xcd_remap;
+    return s;
+}
+
+static void to_cfg(const LaunchShape& s, sdm_launch_config* c)
+{
+    c->group_slots = s.group_slots;
+    c->groups_per_wave = s.groups_per_wave;
+    c->waves_per_block = s.waves_per_block;
+    c->block_threads = s.block_threads;
+    c->xcd_remap = s.xcd_remap;
+}
+
+static sdm_status apply_shape(sdm_ctx* x, const LaunchShape& sh)
+{
+    const bool replan = sh.group_slots != x->shape.group_slots;
+    x->shape = sh;
+    return replan ? upload_plan(x) : SDM_OK;
 }
 
 extern "C" sdm_status sdm_get_launch_config(sdm_ctx* x, sdm_launch_config* cfg)
@@ -347,25 +367,18 @@ extern "C" sdm_status sdm_get_launch_config(sdm_ctx* x, sdm_launch_config* cfg)
         set_error("cfg is NULL");
         return SDM_EINVAL;
     }
-    cfg->cells_per_wave = x->shape.cells_per_wave;
-    cfg->waves_per_block = x->shape.waves_per_block;
-    cfg->block_threads = x->shape.block_threads;
-    cfg->xcd_remap = x->shape.xcd_remap;
+    to_cfg(x->shape, cfg);
     return SDM_OK;
 }
 
 extern "C" sdm_status sdm_set_launch_config(sdm_ctx* x, const sdm_launch_config* cfg)
 {
     SDM_TRY(check_ctx(x));
-    if (!cfg || !shape_valid(*cfg)) {
+    if (!cfg || !shape_valid(from_cfg(*cfg))) {
         set_error("launch config out of range");
         return SDM_EINVAL;
     }
-    x->shape.cells_per_wave = cfg->cells_per_wave;
-    x->shape.waves_per_block = cfg->waves_per_block;
-    x->shape.block_threads = cfg->block_threads;
-    x->shape.xcd_remap = cfg->xcd_remap;
-    return SDM_OK;
+    return apply_shape(x, from_cfg(*cfg));
 }
 
 // ---------------------------------------------------------------- autotune
@@ -405,21 +418,17 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
 
     const LaunchShape original = x->shape;
     std::vector<LaunchShape> cands;
-    for (uint32_t cpw : {1u, 2u, 4u, 8u, 16u})
-        for (uint32_t wpb : {1u, 2u, 4u, 8u})
-            for (uint32_t xr : {0u, 1u}) {
-                LaunchShape c = original;
-                c.cells_per_wave = cpw;
-                c.waves_per_block = wpb;
-                c.xcd_remap = xr;
-                cands.push_back(c);
-            }
-    if (x->n_block > 0)
-        for (uint32_t bt : {256u, 1024u}) {
-            LaunchShape c = original;
-            c.block_threads = bt;
-            cands.push_back(c);
-        }
+    for (uint32_t slots : {256u, 512u})
+        for (uint32_t gpw : {1u, 2u, 4u, 8u})
+            for (uint32_t wpb : {1u, 2u, 4u})
+                for (uint32_t xr : {0u, 1u}) {
+                    LaunchShape c = original;
+                    c.group_slots = slots;
+                    c.groups_per_wave = gpw;
+                    c.waves_per_block = wpb;
+                    c.xcd_remap = xr;
+                    cands.push_back(c);
+                }
     hipEvent_t e0, e1;
     SDM_HIP(hipEventCreate(&e0));
     SDM_HIP(hipEventCreate(&e1));
@@ -427,7 +436,7 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
     LaunchShape best = original;
     sdm_status st = SDM_OK;
     for (const LaunchShape& c : cands) {
-        x->shape = c;
+        if ((st = apply_shape(x, c)) != SDM_OK) break;
         // one untimed step, then reps timed ones
         if ((st = sdm_coalesce_step(x, dt, kernel, seed, 0)) != SDM_OK) break;
         hipEventRecord(e0, s);
@@ -451,14 +460,10 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
     hipStreamSynchronize(s);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    x->shape = (st == SDM_OK) ? best : original;
+    const sdm_status st2 = apply_shape(x, st == SDM_OK ? best : original);
     if (st != SDM_OK) return st;
-    if (best_out) {
-        best_out->cells_per_wave = best.cells_per_wave;
-        best_out->waves_per_block = best.waves_per_block;
-        best_out->block_threads = best.block_threads;
-        best_out->xcd_remap = best.xcd_remap;
-    }
+    if (st2 != SDM_OK) return st2;
+    if (best_out) to_cfg(best, best_out);
     return SDM_OK;
 }
 

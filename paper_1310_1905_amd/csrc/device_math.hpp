@@ -37,18 +37,17 @@ struct Words4 {
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1)
 {
+    // each 32x32 -> 64-bit product is one v_mad_u64_u32 (high and low halves)
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
-        const uint32_t lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo_b = 0xCD9E8D57u * c2;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi_b ^ c1 ^ k0;
-        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo_b;
+        c1 = static_cast<uint32_t>(pb);
         c2 = n2;
-        c3 = lo_a;
+        c3 = static_cast<uint32_t>(pa);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

@@ -2,6 +2,7 @@
 // dispatch of the step kernels over launch shapes.
 #include "runtime.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace sdm {
@@ -128,20 +129,87 @@ sdm_status sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, const d
     return SDM_OK;
 }
 
+// ------------------------------------------------------------ step plan
+void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_cells,
+                uint32_t group_slots)
+{
+    uint32_t g_start = 0, g_slots = 0;
+    bool open = false;
+    for (uint32_t i = 0; i < n_cells; ++i) {
+        const uint32_t c = c_begin + i;
+        const uint32_t n = sizes[i];
+        if (n > group_slots) {
+            if (open) {
+                plan.group_begin.push_back(g_start);
+                plan.group_end.push_back(c);
+                open = false;
+            }
+            plan.block_cells.push_back(c);
+            plan.block_sizes.push_back(n);
+            continue;
+        }
+        if (open && (g_slots + n > group_slots || c - g_start >= static_cast<uint32_t>(kGroupMaxCells))) {
+            plan.group_begin.push_back(g_start);
+            plan.group_end.push_back(c);
+            open = false;
+        }
+        if (!open) {
+            g_start = c;
+            g_slots = 0;
+            open = true;
+        }
+        g_slots += n;
+        ++plan.wave_cells;
+    }
+    if (open) {
+        plan.group_begin.push_back(g_start);
+        plan.group_end.push_back(c_begin + n_cells);
+    }
+}
+
+void plan_finish(Plan& plan)
+{
+    // workgroup tier: largest cells first, so the long ones start early
+    std::vector<uint32_t> idx(plan.block_cells.size());
+    for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+        return plan.block_sizes[a] > plan.block_sizes[b];
+    });
+    std::vector<uint32_t> cells(idx.size()), sizes(idx.size());
+    for (size_t i = 0; i < idx.size(); ++i) {
+        cells[i] = plan.block_cells[idx[i]];
+        sizes[i] = plan.block_sizes[idx[i]];
+    }
+    plan.block_cells.swap(cells);
+    plan.block_sizes.swap(sizes);
+}
+
+bool shape_valid(const LaunchShape& c)
+{
+    const bool waves_ok = c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4;
+    const bool block_ok = c.block_threads == 256 || c.block_threads == 1024;
+    const bool slots_ok = c.group_slots == 256 || c.group_slots == 512;
+    return waves_ok && block_ok && slots_ok && c.groups_per_wave >= 1 && c.groups_per_wave <= 64 &&
+           c.xcd_remap <= 1;
+}
+
 // ------------------------------------------------------------ step launch
-template <bool BATCHED, bool PERM>
-static sdm_status launch_wave(hipStream_t s, const StepArgs& a, uint32_t n_items,
+template <int CAP, bool BATCHED, bool PERM>
+static sdm_status launch_wave(hipStream_t s, const StepArgs& a, uint32_t n_groups,
                               const LaunchShape& sh)
 {
-    const uint64_t per_block = static_cast<uint64_t>(sh.cells_per_wave) * sh.waves_per_block;
-    const uint64_t blocks = (n_items + per_block - 1) / per_block;
+    const uint64_t per_block = static_cast<uint64_t>(sh.groups_per_wave) * sh.waves_per_block;
+    const uint64_t blocks = (n_groups + per_block - 1) / per_block;
+    if (blocks > 0x7FFFFFFFull) {
+        set_error("too many groups for one launch");
+        return SDM_EINVAL;
+    }
     const dim3 grid(static_cast<uint32_t>(blocks));
     switch (sh.waves_per_block) {
-    case 1: hipLaunchKernelGGL((k_wave_cells<1, BATCHED, PERM>), grid, dim3(64), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_wave_cells<2, BATCHED, PERM>), grid, dim3(128), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_wave_cells<4, BATCHED, PERM>), grid, dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_wave_cells<8, BATCHED, PERM>), grid, dim3(512), 0, s, a); break;
-    default: set_error("waves_per_block must be 1, 2, 4 or 8"); return SDM_EINVAL;
+    case 1: hipLaunchKernelGGL((k_wave_groups<CAP, 1, BATCHED, PERM>), grid, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_wave_groups<CAP, 2, BATCHED, PERM>), grid, dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_wave_groups<CAP, 4, BATCHED, PERM>), grid, dim3(256), 0, s, a); break;
+    default: set_error("waves_per_block must be 1, 2 or 4"); return SDM_EINVAL;
     }
     SDM_LAUNCHED();
     return SDM_OK;
@@ -165,20 +233,31 @@ static sdm_status launch_block(hipStream_t s, const StepArgs& a, uint32_t n_item
     return SDM_OK;
 }
 
-sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* wave_items,
-                       uint32_t n_wave, const uint32_t* block_items, uint32_t n_block,
-                       const LaunchShape& shape, bool batched, bool perm)
+template <bool BATCHED, bool PERM>
+static sdm_status launch_wave_any(hipStream_t s, const StepArgs& a, uint32_t n_groups,
+                                  const LaunchShape& sh)
 {
-    if (n_wave > 0) {
+    if (sh.group_slots == 256) return launch_wave<256, BATCHED, PERM>(s, a, n_groups, sh);
+    if (sh.group_slots == 512) return launch_wave<512, BATCHED, PERM>(s, a, n_groups, sh);
+    set_error("group_slots must be 256 or 512");
+    return SDM_EINVAL;
+}
+
+sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* group_begin,
+                       const uint32_t* group_end, uint32_t n_groups, const uint32_t* block_items,
+                       uint32_t n_block, const LaunchShape& shape, bool batched, bool perm)
+{
+    if (n_groups > 0) {
         StepArgs a = base;
-        a.items = wave_items;
-        a.n_items = n_wave;
-        a.cells_per_wave = shape.cells_per_wave;
+        a.group_begin = group_begin;
+        a.group_end = group_end;
+        a.n_groups = n_groups;
+        a.groups_per_wave = shape.groups_per_wave;
         a.xcd_remap = shape.xcd_remap;
-        if (batched) SDM_TRY(perm ? launch_wave<true, true>(s, a, n_wave, shape)
-                                  : launch_wave<true, false>(s, a, n_wave, shape));
-        else SDM_TRY(perm ? launch_wave<false, true>(s, a, n_wave, shape)
-                          : launch_wave<false, false>(s, a, n_wave, shape));
+        if (batched) SDM_TRY(perm ? launch_wave_any<true, true>(s, a, n_groups, shape)
+                                  : launch_wave_any<true, false>(s, a, n_groups, shape));
+        else SDM_TRY(perm ? launch_wave_any<false, true>(s, a, n_groups, shape)
+                          : launch_wave_any<false, false>(s, a, n_groups, shape));
     }
     if (n_block > 0) {
         StepArgs a = base;

@@ -111,17 +111,35 @@ sdm_status sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, const d
                         uint32_t n_cells, const double* dV, SortScratch& scr,
                         uint32_t* offsets, unsigned int* err_dev, const uint32_t** order);
 
-// Launch shape of the step kernels.
+// Launch shape of the step kernels (none of it changes a result).
 struct LaunchShape {
-    uint32_t cells_per_wave = 4;
-    uint32_t waves_per_block = 4;
+    uint32_t group_slots = 512;      // storage slots per wave-tier group (256 or 512)
+    uint32_t groups_per_wave = 2;
+    uint32_t waves_per_block = 1;
     uint32_t block_threads = 256;
-    uint32_t xcd_remap = 1;
+    uint32_t xcd_remap = 0;
 };
 
+// Work lists of one step: wave-tier groups of consecutive cells and
+// workgroup-tier cells (largest first).
+struct Plan {
+    std::vector<uint32_t> group_begin, group_end, block_cells, block_sizes;
+    uint32_t wave_cells = 0;
+};
+
+// Append to `plan` the cells [c_begin, c_end) whose storage-slot counts are
+// sizes[0..): cells above shape.group_slots go to the workgroup tier, the rest
+// are packed greedily into groups of at most group_slots slots and
+// kGroupMaxCells cells.
+void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_cells,
+                uint32_t group_slots);
+void plan_finish(Plan& plan);
+
 // Enqueue the wave-tier and workgroup-tier kernels for one step.
-sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* wave_items,
-                       uint32_t n_wave, const uint32_t* block_items, uint32_t n_block,
-                       const LaunchShape& shape, bool batched, bool perm);
+sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* group_begin,
+                       const uint32_t* group_end, uint32_t n_groups, const uint32_t* block_items,
+                       uint32_t n_block, const LaunchShape& shape, bool batched, bool perm);
+
+bool shape_valid(const LaunchShape& sh);
 
 }  // namespace sdm

@@ -15,8 +15,8 @@
 // the atomic arrival order.
 //
 // Two kernels cover all cell sizes with identical results:
-//   k_wave_cells  -- one 64-lane wavefront per cell, everything in LDS,
-//                    cells of at most kWaveMaxSlots storage slots;
+//   k_wave_groups -- one 64-lane wavefront per group of consecutive cells
+//                    (at most CAP storage slots in all), everything in LDS;
 //   k_block_cells -- one workgroup per cell for larger cells, with the sort
 //                    arrays in a global scratch area (L2-resident) that is
 //                    indexed like the super-droplet arrays.
@@ -27,8 +27,6 @@
 namespace sdm {
 
 constexpr int kWave = 64;
-constexpr int kWaveMaxSlots = 256;                 // storage slots per wave-tier cell
-constexpr int kWaveItems = kWaveMaxSlots / kWave;  // slots per lane
 constexpr int kStatSlots = 64;                     // spread of the global counters
 constexpr int kStatStride = 16;                    // 128 bytes between counter pairs
 
@@ -49,9 +47,13 @@ struct InstanceRec {
 struct StepArgs {
     uint64_t* xi;                 // storage-order multiplicities
     double* r;                    // storage-order radii
-    const uint32_t* items;        // work list of cell-table indices (nullptr: item i = cell i)
+    uint64_t n_sd;                // length of xi and r
+    const uint32_t* items;        // workgroup tier: cell-table indices
     uint32_t n_items;
-    uint32_t cells_per_wave;
+    const uint32_t* group_begin;  // wave tier: first cell of each group
+    const uint32_t* group_end;    // one past the last cell
+    uint32_t n_groups;
+    uint32_t groups_per_wave;
     const uint32_t* off_begin;    // first storage slot of each cell
     const uint32_t* off_end;      // one past the last storage slot
     const double* dV;             // cell volume
@@ -202,196 +204,443 @@ __device__ __forceinline__ bool collide_pair_global(const StepArgs& a, const Cel
 }
 
 // ---------------------------------------------------------------------------
-// Wave tier: one wavefront per cell, at most kWaveMaxSlots storage slots.
+// Wave tier: one wavefront per group of consecutive cells holding at most CAP
+// storage slots (and at most kGroupMaxCells cells), everything staged in LDS.
+// Packing several cells into one wavefront keeps all 64 lanes busy in every
+// phase; per-slot and per-pair lookups go through small LDS tables so that
+// each phase needs one or two dependent LDS round trips.  Collisions are
+// queued in LDS and applied 64 at a time, so the cube-root path runs with
+// full lanes.  The next group's loads are issued before the current group's
+// pair tests, to overlap HBM latency with them.
 // ---------------------------------------------------------------------------
-struct alignas(16) WaveLds {
+constexpr int kGroupMaxCells = 64;
+constexpr int kQueueCap = 128;
+
+struct CollEntry {
+    uint32_t gj, gk;   // storage slots of j (larger multiplicity) and k
+    uint64_t g;        // number of collision events
+};
+
+template <int CAP>
+struct alignas(16) GroupLds {
+    static_assert(CAP % kWave == 0 && CAP <= 512, "group capacity");
+    double dV[kGroupMaxCells];
+    double scale[kGroupMaxCells];           // upscaling factor of eq. (P_ij)
+    uint32_t eqn[kGroupMaxCells];           // first sorted position E | pair base Q << 10 | n << 20
+    uint32_t ucb[kGroupMaxCells];           // first uniform call of the cell
+    CollEntry queue[kQueueCap];             // pending collisions (ring)
     union {
         struct {
-            uint64_t kv[kWaveMaxSlots];            // (key << 32 | slot) grouped by bucket
-            uint32_t keys[kWaveMaxSlots];          // Philox key of every storage slot
-            uint32_t start[kWaveMaxSlots + 4];     // bucket counts, then bucket starts
+            uint64_t kv[CAP];               // (key << 32 | slot) grouped by bucket
+            uint32_t keys[CAP];             // shuffle key of every group slot
+            uint32_t start[CAP + 4];        // bucket counts, then bucket starts
+            uint32_t slotinfo[CAP];         // cell | bucket base << 8 | lg << 24
+            uint32_t call[CAP / 4 + kGroupMaxCells];   // key call: slot base | cell << 9 | q << 15 | (words-1) << 22
         } sort;
         struct {
-            uint64_t xi[kWaveMaxSlots];            // live SDs in shuffle order
-            double r[kWaveMaxSlots];
-            uint32_t slot[kWaveMaxSlots];
+            uint64_t xi[CAP];               // live SDs in sorted order
+            double r[CAP];
+            double u[CAP / 2];              // uniform deviate of every pair
+            uint16_t slot[CAP];
+            uint16_t pairinfo[CAP / 2];     // sorted position of the first member | cell << 10
+            uint32_t ucall[CAP / 4 + kGroupMaxCells];   // first pair | cell << 9 | h << 15 | 2nd valid << 23
         } pairs;
     };
 };
 
-template <int WAVES, bool BATCHED, bool PERM>
-__global__ __launch_bounds__(WAVES * kWave) void k_wave_cells(const StepArgs a)
+struct GroupJob {
+    uint32_t rng_base, step, k0, k1, kernel, inst;
+    double dt;
+    KernelParams kp;
+};
+
+template <bool BATCHED>
+__device__ __forceinline__ GroupJob resolve_group(const StepArgs& a, uint32_t c0)
 {
-    __shared__ WaveLds lds_all[WAVES];
+    GroupJob j;
+    if constexpr (BATCHED) {
+        const uint32_t i = a.cell_inst[c0];
+        const InstanceRec& rec = a.inst[i];
+        j.inst = i;
+        j.rng_base = a.cell_local[c0];
+        j.step = static_cast<uint32_t>(rec.step);
+        j.k0 = static_cast<uint32_t>(rec.seed);
+        j.k1 = static_cast<uint32_t>(rec.seed >> 32);
+        j.kernel = rec.kernel;
+        j.dt = rec.dt;
+        j.kp = rec.kp;
+    } else {
+        j.inst = 0;
+        j.rng_base = c0;
+        j.step = a.step;
+        j.k0 = static_cast<uint32_t>(a.seed);
+        j.k1 = static_cast<uint32_t>(a.seed >> 32);
+        j.kernel = a.kernel;
+        j.dt = a.dt;
+        j.kp = a.kp;
+    }
+    return j;
+}
+
+// Apply `count` queued collisions (one per lane) starting at ring index head.
+// The pair's multiplicities and radii are re-read from global memory: nothing
+// else writes those slots during the step.
+__device__ __forceinline__ void flush_collisions(const StepArgs& a, const CollEntry* queue,
+                                                 uint32_t head, uint32_t count, uint32_t lane)
+{
+    if (lane < count) {
+        const CollEntry e = queue[(head + lane) % kQueueCap];
+        if (e.gj < a.n_sd && e.gk < a.n_sd) {
+            PairState s;
+            s.xj = a.xi[e.gj];
+            s.xk = a.xi[e.gk];
+            s.rj = a.r[e.gj];
+            s.rk = a.r[e.gk];
+            apply_collisions(e.g, s);
+            a.xi[e.gj] = s.xj;
+            a.r[e.gk] = s.rk;
+            if (s.j_changed_r) {
+                a.xi[e.gk] = s.xk;
+                a.r[e.gj] = s.rj;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, uint32_t lane)
+{
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), static_cast<int>(lane)));
+}
+
+// Inclusive sum over the 64 lanes with DPP row shifts and row broadcasts (no LDS).
+__device__ __forceinline__ uint32_t wave_inclusive_sum_dpp(uint32_t v)
+{
+    int x = static_cast<int>(v);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return static_cast<uint32_t>(x);
+}
+
+// The slots of one group in registers, and where they came from.
+template <int K>
+struct GroupRegs {
+    uint32_t c0, c1, g_first, G, o;   // o: first slot of cell c0 + lane (lanes < ncell)
+    uint64_t xv[K];
+    double rv[K];
+};
+
+template <int K, bool PERM>
+__device__ __forceinline__ void fetch_group(const StepArgs& a, uint64_t gi, uint32_t lane,
+                                            GroupRegs<K>& R)
+{
+    R.c0 = a.group_begin[gi];
+    R.c1 = a.group_end[gi];
+    const uint32_t ncell = R.c1 - R.c0;
+    R.o = lane < ncell ? a.off_begin[R.c0 + lane] : 0u;
+    R.g_first = readlane_u32(R.o, 0);
+    R.G = a.off_end[R.c1 - 1] - R.g_first;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t s = lane + k * kWave;
+        R.xv[k] = 0;
+        R.rv[k] = 0.0;
+        if (s < R.G) {
+            R.xv[k] = a.xi[R.g_first + s];
+            if constexpr (!PERM) R.rv[k] = a.r[R.g_first + s];
+        }
+    }
+}
+
+template <int CAP, int WAVES, bool BATCHED, bool PERM>
+__global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
+{
+    using Lds = GroupLds<CAP>;
+    constexpr int K = CAP / kWave;   // storage slots per lane
+    __shared__ Lds lds_all[WAVES];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = threadIdx.x / kWave;
-    WaveLds& L = lds_all[wv];
+    Lds& L = lds_all[wv];
+    const unsigned long long lanes_lt = (1ull << lane) - 1ull;
 
     const uint32_t blk = a.xcd_remap ? xcd_contiguous_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const uint64_t wave_id = static_cast<uint64_t>(blk) * WAVES + wv;
-    uint64_t it = wave_id * a.cells_per_wave;
-    const uint64_t it_stop = it + a.cells_per_wave;
-    const uint64_t it_end = it_stop < a.n_items ? it_stop : static_cast<uint64_t>(a.n_items);
+    uint64_t g = wave_id * a.groups_per_wave;
+    const uint64_t g_stop = g + a.groups_per_wave;
+    const uint64_t g_end = g_stop < a.n_groups ? g_stop : static_cast<uint64_t>(a.n_groups);
 
+    uint32_t q_head = 0, q_count = 0;
     unsigned long long pair_acc = 0, coll_acc = 0;
+    GroupRegs<K> R;
+    if (g < g_end) fetch_group<K, PERM>(a, g, lane, R);
 
-    for (; it < it_end; ++it) {
-        const uint32_t c = a.items ? a.items[it] : static_cast<uint32_t>(it);
-        const CellJob j = resolve_cell<BATCHED>(a, c);
-        const uint32_t N = j.n_slots;
-        if (N > static_cast<uint32_t>(kWaveMaxSlots)) continue;   // never planned here
+    for (; g < g_end; ++g) {
+        const uint32_t c0 = R.c0;
+        const uint32_t ncell = R.c1 - c0;
+        const uint32_t g_first = R.g_first;
+        const uint32_t G = R.G;
+        const GroupJob job = resolve_group<BATCHED>(a, c0);
 
-        // (1) load the cell and count the live super-droplets
-        uint64_t xv[kWaveItems];
-        double rv[kWaveItems];
-        uint32_t n = 0;
+        // (1) live SDs: per-item ballots; live slots before each cell's first slot
+        unsigned long long live[K];
+        uint32_t n_tot = 0;
 #pragma unroll
-        for (int k = 0; k < kWaveItems; ++k) {
-            const uint32_t s = lane + k * kWave;
-            xv[k] = 0;
-            rv[k] = 0.0;
-            if (s < N) {
-                xv[k] = a.xi[j.off + s];
-                if constexpr (!PERM) rv[k] = a.r[j.off + s];
-            }
-            n += static_cast<uint32_t>(__popcll(__ballot(xv[k] != 0)));
+        for (int k = 0; k < K; ++k) {
+            live[k] = __ballot(R.xv[k] != 0);
+            n_tot += static_cast<uint32_t>(__popcll(live[k]));
         }
-        if (n < 2) {
-            if constexpr (PERM) {
-                if (lane == 0) a.nlive_out[c] = n;
+        const uint32_t first = R.o - g_first;                       // lanes < ncell
+        uint32_t before = 0;
 #pragma unroll
-                for (int k = 0; k < kWaveItems; ++k)
-                    if (xv[k] != 0) a.perm_out[j.off] = lane + k * kWave;
-            }
+        for (int k = 0; k < K; ++k) {
+            const uint32_t kb = static_cast<uint32_t>(k) * kWave;
+            if (first >= kb + kWave) before += static_cast<uint32_t>(__popcll(live[k]));
+            else if (first > kb) before += static_cast<uint32_t>(__popcll(live[k] & ((1ull << (first - kb)) - 1ull)));
+        }
+        const uint32_t before_next = __shfl_down(before, 1, kWave);
+        const uint32_t first_next = __shfl_down(first, 1, kWave);
+        const bool has_cell = lane < ncell;
+        const bool last_cell = lane + 1 == ncell;
+        const uint32_t nl = has_cell ? ((last_cell ? n_tot : before_next) - before) : 0u;
+        const uint32_t n_slots_l = has_cell ? ((last_cell ? G : first_next) - first) : 0u;
+        const uint32_t lgl = nl ? 31u - static_cast<uint32_t>(__clz(static_cast<int>(nl))) : 0u;
+        const uint32_t nbl = nl ? (1u << lgl) : 0u;               // 2^floor(log2 n) buckets
+        const uint32_t calls_l = (n_slots_l + 3u) >> 2;            // Philox calls for the keys
+        // one scan for bucket bases (bits 0..9), pair bases (10..19) and call bases (20..27)
+        const uint32_t packed = nbl | ((nl >> 1) << 10) | (calls_l << 20);
+        const uint32_t incl = wave_inclusive_sum_dpp(packed);
+        const uint32_t excl = incl - packed;
+        const uint32_t tot = readlane_u32(incl, kWave - 1);
+        const uint32_t nb_tot = tot & 1023u;
+        const uint32_t q_tot = (tot >> 10) & 1023u;
+        const uint32_t p_tot = tot >> 20;
+        const uint32_t b_base = excl & 1023u;
+        const uint32_t q_base = (excl >> 10) & 1023u;
+        const uint32_t p_base = excl >> 20;
+        // uniform deviates: one Philox call per two pairs of a cell
+        const uint32_t ucalls_l = ((nl >> 1) + 1u) >> 1;
+        const uint32_t u_incl = wave_inclusive_sum_dpp(ucalls_l);
+        const uint32_t u_tot = readlane_u32(u_incl, kWave - 1);
+        if (has_cell) {
+            L.ucb[lane] = u_incl - ucalls_l;
+            L.eqn[lane] = before | (q_base << 10) | (nl << 20);
+            L.dV[lane] = a.dV[c0 + lane];
+            L.scale[lane] = nl >= 2 ? upscale_factor(nl) : 0.0;
+            if constexpr (PERM) a.nlive_out[c0 + lane] = nl;
+        }
+        if (n_tot == 0 || (!PERM && q_tot == 0)) {
+            wave_sync();
+            if (g + 1 < g_end) fetch_group<K, PERM>(a, g + 1, lane, R);
             continue;
         }
-        const uint32_t lg = ceil_log2(n);
-        const uint32_t nb = 1u << lg;
+        // per-slot info and per-call info, one cell at a time
+        const uint32_t info_l = lane | (b_base << 8) | (lgl << 24);
+        for (uint32_t c = 0; c < ncell; ++c) {
+            const uint32_t sb = readlane_u32(first, c);
+            const uint32_t sn = readlane_u32(n_slots_l, c);
+            const uint32_t info = readlane_u32(info_l, c);
+            const uint32_t pb = readlane_u32(p_base, c);
+            const uint32_t pn = readlane_u32(calls_l, c);
+            for (uint32_t s = lane; s < sn; s += kWave) L.sort.slotinfo[sb + s] = info;
+            for (uint32_t q = lane; q < pn; q += kWave) {
+                const uint32_t words = (sn - 4 * q) < 4u ? (sn - 4 * q) : 4u;
+                L.sort.call[pb + q] = (sb + 4 * q) | (c << 9) | (q << 15) | ((words - 1u) << 22);
+            }
+        }
+        for (uint32_t i = lane; i <= nb_tot; i += kWave) L.sort.start[i] = 0;
+        wave_sync();
 
-        // (2) keys: lane q draws the four keys of slots 4q..4q+3
-        for (uint32_t i = lane; i <= nb; i += kWave) L.sort.start[i] = 0;
-        for (uint32_t q = lane; 4 * q < N; q += kWave) {
-            const Words4 w = philox4x32_10(q, j.rng_cell, j.step, kTagShuffle, j.k0, j.k1);
-            uint4 v;
-            v.x = w.w[0];
-            v.y = w.w[1];
-            v.z = w.w[2];
-            v.w = w.w[3];
-            *reinterpret_cast<uint4*>(&L.sort.keys[4 * q]) = v;
+        // (2) keys: call i draws the four keys of local slots 4q..4q+3 of its cell
+        for (uint32_t i = lane; i < p_tot; i += kWave) {
+            const uint32_t ci = L.sort.call[i];
+            const uint32_t base = ci & 511u;
+            const uint32_t c = (ci >> 9) & 63u;
+            const uint32_t q = (ci >> 15) & 127u;
+            const uint32_t words = (ci >> 22) + 1u;
+            const Words4 w = philox4x32_10(q, job.rng_base + c, job.step, kTagShuffle, job.k0, job.k1);
+#pragma unroll
+            for (uint32_t t = 0; t < 4; ++t)
+                if (t < words) L.sort.keys[base + t] = w.w[t];
         }
         wave_sync();
 
-        // bucket counts (atomic arrival index kept for the scatter)
-        uint32_t key[kWaveItems], arrival[kWaveItems];
+        // bucket counts
+        uint32_t key[K], bkt[K], arr[K], cid[K];
 #pragma unroll
-        for (int k = 0; k < kWaveItems; ++k) {
-            const uint32_t s = lane + k * kWave;
+        for (int k = 0; k < K; ++k) {
             key[k] = 0;
-            arrival[k] = 0;
-            if (xv[k] != 0) {
+            bkt[k] = 0;
+            arr[k] = 0;
+            cid[k] = 0;
+            if (R.xv[k] != 0) {
+                const uint32_t s = lane + k * kWave;
+                const uint32_t si = L.sort.slotinfo[s];
                 key[k] = L.sort.keys[s];
-                arrival[k] = atomicAdd(&L.sort.start[bucket_of(key[k], lg)], 1u);
+                cid[k] = si & 255u;
+                bkt[k] = ((si >> 8) & 1023u) + bucket_of(key[k], si >> 24);
+                arr[k] = atomicAdd(&L.sort.start[bkt[k]], 1u);
             }
         }
         wave_sync();
 
-        // exclusive scan of the nb bucket counts; start[nb] = n
+        // exclusive scan of the nb_tot bucket counts; start[nb_tot] = n_tot
         {
-            const uint32_t per = (nb + kWave - 1) / kWave;   // 1..4
+            const uint32_t per = (nb_tot + kWave - 1) / kWave;   // <= K
             const uint32_t base = lane * per;
-            uint32_t v[kWaveItems];
+            uint32_t v[K];
             uint32_t sum = 0;
 #pragma unroll
-            for (int t = 0; t < kWaveItems; ++t) {
+            for (int t = 0; t < K; ++t) {
                 v[t] = 0;
-                if (static_cast<uint32_t>(t) < per && base + t < nb) v[t] = L.sort.start[base + t];
+                if (static_cast<uint32_t>(t) < per && base + t < nb_tot) v[t] = L.sort.start[base + t];
                 sum += v[t];
             }
-            const uint32_t incl = wave_inclusive_sum(sum, lane);
-            uint32_t run = incl - sum;
+            const uint32_t inc = wave_inclusive_sum_dpp(sum);
+            uint32_t run = inc - sum;
 #pragma unroll
-            for (int t = 0; t < kWaveItems; ++t) {
-                if (static_cast<uint32_t>(t) < per && base + t < nb) L.sort.start[base + t] = run;
+            for (int t = 0; t < K; ++t) {
+                if (static_cast<uint32_t>(t) < per && base + t < nb_tot) L.sort.start[base + t] = run;
                 run += v[t];
             }
-            if (lane == kWave - 1) L.sort.start[nb] = incl;
+            if (lane == kWave - 1) L.sort.start[nb_tot] = inc;
         }
         wave_sync();
 
         // scatter (key, slot) to bucket start + arrival
 #pragma unroll
-        for (int k = 0; k < kWaveItems; ++k) {
-            if (xv[k] != 0) {
-                const uint32_t s = lane + k * kWave;
-                const uint32_t pos = L.sort.start[bucket_of(key[k], lg)] + arrival[k];
-                L.sort.kv[pos] = (static_cast<uint64_t>(key[k]) << 32) | s;
-            }
-        }
+        for (int k = 0; k < K; ++k)
+            if (R.xv[k] != 0)
+                L.sort.kv[L.sort.start[bkt[k]] + arr[k]] =
+                    (static_cast<uint64_t>(key[k]) << 32) | (lane + k * kWave);
         wave_sync();
 
         // rank inside the bucket by full (key, slot) comparison
-        uint32_t final_pos[kWaveItems];
+        uint32_t pos[K];
 #pragma unroll
-        for (int k = 0; k < kWaveItems; ++k) {
-            final_pos[k] = 0;
-            if (xv[k] != 0) {
-                const uint32_t s = lane + k * kWave;
-                const uint32_t b = bucket_of(key[k], lg);
-                const uint32_t lo = L.sort.start[b];
-                const uint32_t hi = L.sort.start[b + 1];
-                const uint64_t me = (static_cast<uint64_t>(key[k]) << 32) | s;
+        for (int k = 0; k < K; ++k) {
+            pos[k] = 0;
+            if (R.xv[k] != 0) {
+                const uint32_t lo = L.sort.start[bkt[k]];
+                const uint32_t hi = L.sort.start[bkt[k] + 1];
+                const uint64_t me = (static_cast<uint64_t>(key[k]) << 32) | (lane + k * kWave);
                 uint32_t rank = 0;
                 for (uint32_t e = lo; e < hi; ++e) rank += (L.sort.kv[e] < me) ? 1u : 0u;
-                final_pos[k] = lo + rank;
+                pos[k] = lo + rank;
             }
         }
-        wave_sync();   // every read of the sort arrays is done before they are overwritten
+        wave_sync();   // the sort arrays are overwritten below
 
+        // (3) place the live SDs in sorted order; note the first member of each pair
 #pragma unroll
-        for (int k = 0; k < kWaveItems; ++k) {
-            if (xv[k] != 0) {
-                const uint32_t p = final_pos[k];
-                L.pairs.xi[p] = xv[k];
-                L.pairs.r[p] = rv[k];
-                L.pairs.slot[p] = lane + k * kWave;
+        for (int k = 0; k < K; ++k) {
+            if (R.xv[k] != 0) {
+                const uint32_t s = lane + k * kWave;
+                const uint32_t p = pos[k];
+                const uint32_t eqn = L.eqn[cid[k]];
+                const uint32_t loc = p - (eqn & 1023u);
+                if constexpr (!PERM) {
+                    L.pairs.xi[p] = R.xv[k];
+                    L.pairs.r[p] = R.rv[k];
+                    L.pairs.slot[p] = static_cast<uint16_t>(s);
+                    const uint32_t n_c = eqn >> 20;
+                    if (!(loc & 1u) && loc + 1 < n_c) {
+                        const uint32_t q = ((eqn >> 10) & 1023u) + (loc >> 1);
+                        L.pairs.pairinfo[q] = static_cast<uint16_t>(p | (cid[k] << 10));
+                        if (!(loc & 3u))   // first pair of a uniform call
+                            L.pairs.ucall[L.ucb[cid[k]] + (loc >> 2)] =
+                                q | (cid[k] << 9) | ((loc >> 2) << 15) | ((loc + 3 < n_c ? 1u : 0u) << 23);
+                    }
+                }
+            }
+        }
+        if constexpr (PERM) {
+            // local slot of the SD at sorted position loc of its cell
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                // the shuffle runs with every lane active (an inactive source lane reads as 0)
+                const uint32_t cell_first = __shfl(first, cid[k], kWave);
+                if (R.xv[k] != 0) {
+                    const uint32_t s = lane + k * kWave;
+                    const uint32_t eqn = L.eqn[cid[k]];
+                    const uint32_t loc = pos[k] - (eqn & 1023u);
+                    a.perm_out[g_first + cell_first + loc] = s - cell_first;
+                }
             }
         }
         wave_sync();
+        // the registers of this group are free: start loading the next one
+        if (g + 1 < g_end) fetch_group<K, PERM>(a, g + 1, lane, R);
+        if constexpr (PERM) continue;
 
-        if constexpr (PERM) {
-            for (uint32_t i = lane; i < n; i += kWave) a.perm_out[j.off + i] = L.pairs.slot[i];
-            if (lane == 0) a.nlive_out[c] = n;
-            wave_sync();
-            continue;
+        // (4) uniform deviates, two pairs per Philox call
+        for (uint32_t i = lane; i < u_tot; i += kWave) {
+            const uint32_t uc = L.pairs.ucall[i];
+            const uint32_t q = uc & 511u;
+            const uint32_t c = (uc >> 9) & 63u;
+            const uint32_t h = (uc >> 15) & 255u;
+            const Words4 w = philox4x32_10(h, job.rng_base + c, job.step, kTagUniform, job.k0, job.k1);
+            L.pairs.u[q] = uniform_open01(w.w[0], w.w[1]);
+            if (uc >> 23) L.pairs.u[q + 1] = uniform_open01(w.w[2], w.w[3]);
         }
+        wave_sync();
 
-        // (3) pairs (2m, 2m+1)
-        const uint32_t npairs = n >> 1;
-        const double scale = upscale_factor(n);
+        // (5) pair tests; colliding pairs go to the queue
         uint32_t coll = 0;
-        for (uint32_t m = lane; m < npairs; m += kWave) {
-            const double u = pair_uniform(m, j.rng_cell, j.step, j.k0, j.k1);
-            const ulonglong2 x2 = *reinterpret_cast<const ulonglong2*>(&L.pairs.xi[2 * m]);
-            const double2 r2 = *reinterpret_cast<const double2*>(&L.pairs.r[2 * m]);
-            const uint2 s2 = *reinterpret_cast<const uint2*>(&L.pairs.slot[2 * m]);
-            if (collide_pair_global(a, j, scale, u, s2.x, s2.y, x2.x, x2.y, r2.x, r2.y)) ++coll;
+        for (uint32_t qb = 0; qb < q_tot; qb += kWave) {
+            const uint32_t q = qb + lane;
+            uint64_t gam = 0;
+            uint32_t gj = 0, gk = 0;
+            if (q < q_tot) {
+                const uint32_t pi = L.pairs.pairinfo[q];
+                const uint32_t p = pi & 1023u;
+                const uint32_t c = pi >> 10;
+                const uint32_t sa = L.pairs.slot[p], sb = L.pairs.slot[p + 1];
+                const uint64_t xa = L.pairs.xi[p], xb = L.pairs.xi[p + 1];
+                const double ra = L.pairs.r[p], rb = L.pairs.r[p + 1];
+                const double u = L.pairs.u[q];
+                const double Kab = collection_kernel(job.kernel, job.kp, ra, rb);
+                const bool a_is_j = xa >= xb;
+                const uint64_t xj = a_is_j ? xa : xb;
+                const uint64_t xk = a_is_j ? xb : xa;
+                const double prob = collision_probability(xj, Kab, job.dt, L.dV[c], L.scale[c]);
+                gam = collision_count(prob, u, xj, xk);
+                gj = g_first + (a_is_j ? sa : sb);
+                gk = g_first + (a_is_j ? sb : sa);
+            }
+            const unsigned long long hit = __ballot(gam != 0);
+            if (gam != 0) {
+                const uint32_t idx =
+                    (q_head + q_count + static_cast<uint32_t>(__popcll(hit & lanes_lt))) % kQueueCap;
+                L.queue[idx].gj = gj;
+                L.queue[idx].gk = gk;
+                L.queue[idx].g = gam;
+            }
+            const uint32_t nh = static_cast<uint32_t>(__popcll(hit));
+            q_count += nh;
+            coll += nh;
+            if (q_count >= static_cast<uint32_t>(kWave)) {
+                wave_sync();
+                flush_collisions(a, L.queue, q_head, kWave, lane);
+                q_head = (q_head + kWave) % kQueueCap;
+                q_count -= kWave;
+                wave_sync();
+            }
         }
-        wave_sync();   // pair reads done before the next cell reuses the LDS
-
-        // counters
-        unsigned long long cell_coll = 0;
-        {
-            // wave total of per-lane collision counts
-            uint32_t v = coll;
-#pragma unroll
-            for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-            cell_coll = v;
-        }
+        wave_sync();   // pair reads done before the next group reuses the LDS
         if constexpr (BATCHED) {
-            if (lane == 0) add_counts(a, true, j.inst, 0, npairs, cell_coll);
+            if (lane == 0) add_counts(a, true, job.inst, 0, q_tot, coll);
         } else {
-            pair_acc += npairs;
-            coll_acc += cell_coll;
+            pair_acc += q_tot;
+            coll_acc += coll;
+        }
+    }
+    if constexpr (!PERM) {
+        if (q_count > 0) {
+            wave_sync();
+            flush_collisions(a, L.queue, q_head, q_count, lane);
         }
     }
     if constexpr (!BATCHED && !PERM) {

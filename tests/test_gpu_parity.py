@@ -44,7 +44,7 @@ def _run_pair(sdm_mod, oracle_mod, pop, steps, dt, kernel, dV_scale=1.0, threads
 
 
 @pytest.mark.parametrize("kernel", ["geometric", "golovin"])
-@pytest.mark.parametrize("max_per_cell", [40, 256, 257, 900])
+@pytest.mark.parametrize("max_per_cell", [3, 40, 256, 257, 512, 513, 900])
 def test_ragged_cells(sdm_mod, oracle_mod, kernel, max_per_cell):
     pop = synth.tiny_cells(seed=100 + max_per_cell, n_cells=150, max_per_cell=max_per_cell,
                            xi_max=60)
@@ -53,7 +53,7 @@ def test_ragged_cells(sdm_mod, oracle_mod, kernel, max_per_cell):
     assert ref.stats[1] > 0
 
 
-@pytest.mark.parametrize("max_per_cell", [40, 700])
+@pytest.mark.parametrize("max_per_cell", [40, 300, 700])
 def test_permutation_bit_exact(sdm_mod, oracle_mod, max_per_cell):
     pop = synth.tiny_cells(seed=7, n_cells=120, max_per_cell=max_per_cell, dead_fraction=0.3)
     ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV)
@@ -66,6 +66,38 @@ def test_permutation_bit_exact(sdm_mod, oracle_mod, max_per_cell):
             exp = oracle_mod.cell_order(ref.xi[off[c]:off[c + 1]], 31337, c, step)
             assert nlive[c] == exp.size
             assert np.array_equal(order[off[c]:off[c] + exp.size], exp), (step, c)
+
+
+@pytest.mark.parametrize("shape", [
+    dict(group_slots=256, groups_per_wave=1, waves_per_block=1, xcd_remap=0),
+    dict(group_slots=256, groups_per_wave=3, waves_per_block=4, xcd_remap=1),
+    dict(group_slots=512, groups_per_wave=1, waves_per_block=2, xcd_remap=0),
+    dict(group_slots=512, groups_per_wave=8, waves_per_block=4, xcd_remap=1, block_threads=1024),
+])
+def test_launch_shapes_give_identical_results(sdm_mod, oracle_mod, shape):
+    pop = synth.tiny_cells(seed=55, n_cells=700, max_per_cell=600, xi_max=40)
+    ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV * 1e-4)
+    ctx.set_launch_config(**shape)
+    ref = oracle_mod.SlotState(pop.cell, pop.xi, pop.r, pop.dV * 1e-4)
+    for t in range(6):
+        ctx.step(3.0, "geometric", pop.seed, t)
+        ref.step_parallel(3.0, oracle_mod.GEOMETRIC, pop.seed, t, threads=8)
+    _assert_same(ctx, ref, f"shape {shape}")
+    order, nlive = ctx.permutation(seed=3, step=7)
+    off = ref.offsets.astype(np.int64)
+    order, nlive = order.cpu().numpy(), nlive.cpu().numpy()
+    for c in range(0, ref.n_cells, 7):
+        exp = oracle_mod.cell_order(ref.xi[off[c]:off[c + 1]], 3, c, 7)
+        assert nlive[c] == exp.size and np.array_equal(order[off[c]:off[c] + exp.size], exp)
+
+
+def test_many_cells_per_group(sdm_mod, oracle_mod):
+    """Runs of tiny and empty cells: groups reach the 64-cell limit."""
+    pop = synth.tiny_cells(seed=8, n_cells=3000, max_per_cell=4, xi_max=9, dead_fraction=0.2)
+    ctx, ref = _run_pair(sdm_mod, oracle_mod, pop, 8, 5.0, "golovin", dV_scale=1e-9)
+    _assert_same(ctx, ref, "tiny cells")
+    groups, wave_cells, block_cells = ctx.plan()
+    assert wave_cells == pop.n_cells and block_cells == 0 and groups <= pop.n_cells // 64 + 60
 
 
 def test_empty_and_degenerate_inputs(sdm_mod, oracle_mod):
@@ -120,7 +152,7 @@ def test_box_golovin(sdm_mod, oracle_mod):
     pop = synth.box_golovin(seed=synth.SEEDS[2])
     ctx, ref = _run_pair(sdm_mod, oracle_mod, pop, 400, pop.dt, pop.kernel, threads=1)
     _assert_same(ctx, ref, "box golovin 400 steps")
-    assert ctx.plan() == (0, 1)
+    assert ctx.plan()[1:] == (0, 1)
 
 
 def test_large_domain_reduced_full_parity(sdm_mod, oracle_mod):
