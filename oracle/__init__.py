@@ -83,6 +83,14 @@ def lib() -> ctypes.CDLL:
     L.oracle_step.restype = i32
     L.oracle_sort_by_cell.argtypes = [u64, P, u32, P, P]
     L.oracle_sort_by_cell.restype = i32
+    L.oracle_moments.argtypes = [u32, P, P, P, P, i32, dbl, dbl, P, P]
+    L.oracle_moments.restype = None
+    L.oracle_moment_cell.argtypes = [u32, P, P, i32, dbl, dbl, dbl, dbl]
+    L.oracle_moment_cell.restype = dbl
+    L.oracle_sd_conc.argtypes = [u32, P, P, P]
+    L.oracle_sd_conc.restype = None
+    L.oracle_max_probability.argtypes = [u32, P, P, P, P, dbl, i32, P, u64, u32, u32]
+    L.oracle_max_probability.restype = dbl
     _lib = L
     return L
 
@@ -221,6 +229,26 @@ class SlotState:
                           self.r[base:].ctypes.data, dt, kind, _ptr(p), seed, step, c0,
                           _ptr(st))
         return st
+
+    def moments(self, k: int, r_min: float = 0.0, r_max: float = float("inf"), rho_d=None):
+        """Per-cell k-th moment of the radius distribution, (rho_d dV)^-1 sum N r^k."""
+        out = np.zeros(self.n_cells)
+        rho = None if rho_d is None else np.ascontiguousarray(rho_d, dtype=np.float64)
+        lib().oracle_moments(self.n_cells, _ptr(self.offsets), _ptr(self.dV), _ptr(self.xi),
+                             _ptr(self.r), k, r_min, r_max,
+                             None if rho is None else _ptr(rho), _ptr(out))
+        return out
+
+    def sd_conc(self):
+        out = np.zeros(self.n_cells, dtype=np.uint32)
+        lib().oracle_sd_conc(self.n_cells, _ptr(self.offsets), _ptr(self.xi), _ptr(out))
+        return out
+
+    def max_probability(self, dt, kind, seed, step, params=None):
+        p = _params(params)
+        return float(lib().oracle_max_probability(self.n_cells, _ptr(self.offsets), _ptr(self.dV),
+                                                  _ptr(self.xi), _ptr(self.r), dt, kind, _ptr(p),
+                                                  seed, step, 0))
 
     def input_order(self):
         """(xi, r) scattered back to input order."""

@@ -5,7 +5,10 @@
  * coalescence step of the Super-Droplet Method (SDM), as the particle-based
  * scheme of libcloudph++ 0.2 (Arabas, Jaruga, Pawlowska, Grabowski) states it
  * in Sect. 5.1.4 "Coalescence", eq. (P_ij), extended by multiple coalescence
- * with the gamma-capping rule (see oracle_collide_pair).
+ * with the gamma-capping rule (see oracle_collide_pair), plus the gridded
+ * diagnostics of the particle-based scheme (super-droplet concentration and
+ * radius moments per cell) and a probe of the largest collision probability a
+ * step would meet.
  *
  * It exists to check the HIP library.  Only the tests, the smoke check and the
  * CPU-baseline leg of the benchmark may load it.  It shares no code, header,
@@ -26,7 +29,11 @@
  *   - equal multiplicities after the collision split xi_k in two halves
  *     (instead of leaving a zero-multiplicity particle for recycling);
  *   - random numbers from counter-based Philox4x32-10 instead of the
- *     Mersenne Twister the paper's release uses (Sect. 5.3).
+ *     Mersenne Twister the paper's release uses (Sect. 5.3);
+ *   - moments count live super-droplets only, the radius range is closed at
+ *     both ends, and rho_d defaults to 1 (moments per unit volume) when no
+ *     dry-air density is given; the summation order is fixed (see
+ *     oracle_moment_cell) so that any implementation can match it bit for bit.
  */
 #include <math.h>
 #include <stdint.h>
@@ -427,4 +434,83 @@ int oracle_sort_by_cell(uint64_t n_sd, const uint32_t *cell, uint32_t n_cells,
     }
     free(fill);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gridded diagnostics (the particle-based scheme's diag_sd_conc and        */
+/* diag_wet_mom of Sect. 5.2): per cell, the number of live super-droplets   */
+/* and the k-th moment  M = (rho_d dV)^-1 sum_{r_i in [r_min, r_max]} N_i r_i^k */
+/* over live super-droplets.                                                */
+/* Summation order (fixed, so results are reproducible bit for bit): the    */
+/* cell's slots are dealt to 64 partial sums by slot index modulo 64, each   */
+/* summed in ascending slot order; the partials are then added pairwise,     */
+/* partial[l] += partial[l + d] for d = 32, 16, 8, 4, 2, 1.                  */
+/* ------------------------------------------------------------------------ */
+double oracle_moment_cell(uint32_t n_slots, const uint64_t *xi, const double *r, int k,
+                          double r_min, double r_max, double rho_d, double dV)
+{
+    double part[64];
+    for (int l = 0; l < 64; ++l) part[l] = 0.0;
+    for (uint32_t s = 0; s < n_slots; ++s) {
+        if (xi[s] == 0 || !(r[s] >= r_min && r[s] <= r_max)) continue;
+        double rk = 1.0;
+        for (int i = 0; i < k; ++i) rk = rk * r[s];
+        part[s % 64u] = part[s % 64u] + (double)xi[s] * rk;
+    }
+    for (int d = 32; d >= 1; d /= 2)
+        for (int l = 0; l < d; ++l) part[l] = part[l] + part[l + d];
+    return part[0] / (rho_d * dV);
+}
+
+void oracle_moments(uint32_t n_cells, const uint64_t *offsets, const double *dV,
+                    const uint64_t *xi, const double *r, int k, double r_min, double r_max,
+                    const double *rho_d, double *out)
+{
+    for (uint32_t c = 0; c < n_cells; ++c) {
+        uint64_t b = offsets[c];
+        out[c] = oracle_moment_cell((uint32_t)(offsets[c + 1] - b), xi + b, r + b, k, r_min,
+                                    r_max, rho_d ? rho_d[c] : 1.0, dV[c]);
+    }
+}
+
+void oracle_sd_conc(uint32_t n_cells, const uint64_t *offsets, const uint64_t *xi, uint32_t *out)
+{
+    for (uint32_t c = 0; c < n_cells; ++c) {
+        uint32_t n = 0;
+        for (uint64_t s = offsets[c]; s < offsets[c + 1]; ++s) n += xi[s] != 0;
+        out[c] = n;
+    }
+}
+
+/* Largest collision probability over the pairs one step would test (the
+ * quantity an adaptive sub-step would be chosen from); the state is not
+ * changed. */
+double oracle_max_probability(uint32_t n_cells, const uint64_t *offsets, const double *dV,
+                              const uint64_t *xi, const double *r, double dt, int kernel,
+                              const double *params, uint64_t seed, uint32_t step,
+                              uint32_t cell_index_base)
+{
+    double pmax = 0.0;
+    uint32_t max_slots = 0;
+    for (uint32_t c = 0; c < n_cells; ++c) {
+        uint64_t cnt = offsets[c + 1] - offsets[c];
+        if (cnt > max_slots) max_slots = (uint32_t)cnt;
+    }
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (max_slots ? max_slots : 1));
+    for (uint32_t c = 0; c < n_cells; ++c) {
+        uint64_t base = offsets[c];
+        uint32_t n = oracle_cell_order((uint32_t)(offsets[c + 1] - base), xi + base, seed,
+                                       cell_index_base + c, step, order);
+        if (n < 2) continue;
+        double scale = oracle_upscale(n);
+        for (uint32_t m = 0; m < n / 2u; ++m) {
+            uint64_t a = base + order[2u * m], b = base + order[2u * m + 1u];
+            uint64_t xj = xi[a] >= xi[b] ? xi[a] : xi[b];
+            double K = oracle_kernel(kernel, params, r[a], r[b]);
+            double p = oracle_probability(xj, K, dt, dV[c], scale);
+            if (p > pmax) pmax = p;
+        }
+    }
+    free(order);
+    return pmax;
 }
