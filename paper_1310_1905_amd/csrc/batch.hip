@@ -107,6 +107,7 @@ struct BatchLayout {
     uint32_t* group_begin;
     uint32_t* group_end;
     uint32_t* block_items;
+    GridArrays grid;
     unsigned int* err;
     uint32_t* local_off;     // admission: offsets of the instance being added
     uint64_t* scr_kv;
@@ -134,6 +135,7 @@ BatchLayout batch_layout(void* ws, size_t bytes, uint64_t max_sd, uint32_t max_c
     L.group_begin = cv.take<uint32_t>(max_cells);
     L.group_end = cv.take<uint32_t>(max_cells);
     L.block_items = cv.take<uint32_t>(max_cells);
+    carve_grid(cv, max_sd, &L.grid);
     L.err = cv.take<unsigned int>(64);
     L.local_off = cv.take<uint32_t>(uint64_t(max_cells) + 1);
     // step scratch and admission sort scratch share one region (admission
@@ -187,6 +189,7 @@ static sdm_status rebuild_lists(sdm_batch* b)
     if (!plan.block_cells.empty())
         SDM_HIP(hipMemcpyAsync(b->L.block_items, plan.block_cells.data(),
                                plan.block_cells.size() * 4, hipMemcpyHostToDevice, b->stream));
+    SDM_TRY(upload_grid(b->stream, plan, &b->L.grid));
     SDM_HIP(hipStreamSynchronize(b->stream));
     b->n_groups = static_cast<uint32_t>(ng);
     b->n_block = static_cast<uint32_t>(plan.block_cells.size());
@@ -210,6 +213,7 @@ static sdm_status enqueue_step(sdm_batch* b)
     a.scr_tmp = b->L.scr_tmp;
     a.scr_pos = b->L.scr_pos;
     a.scr_cnt = b->L.scr_cnt;
+    grid_args(b->L.grid, &a);
     SDM_TRY(launch_step(b->stream, a, b->L.group_begin, b->L.group_end, b->n_groups,
                         b->L.block_items, b->n_block, b->shape, true, false));
     hipLaunchKernelGGL(k_advance_instances, dim3(grid_for(b->max_inst, 256, 1024)), dim3(256), 0,

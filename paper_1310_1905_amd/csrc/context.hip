@@ -21,6 +21,7 @@ struct sdm_ctx {
     uint32_t* group_begin = nullptr;
     uint32_t* group_end = nullptr;
     uint32_t* block_items = nullptr;
+    GridArrays grid;
     unsigned long long* stats = nullptr;
     unsigned int* err = nullptr;
     uint64_t* scr_kv = nullptr;
@@ -44,6 +45,7 @@ struct CtxLayout {
     uint32_t* group_begin;
     uint32_t* group_end;
     uint32_t* block_items;
+    GridArrays grid;
     unsigned long long* stats;
     unsigned int* err;
     // scratch (workgroup-tier sort arrays during steps; sort-by-cell arrays during init)
@@ -67,6 +69,7 @@ CtxLayout layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t c)
     L.group_begin = cv.take<uint32_t>(c);
     L.group_end = cv.take<uint32_t>(c);
     L.block_items = cv.take<uint32_t>(c);
+    carve_grid(cv, n, &L.grid);
     L.stats = cv.take<unsigned long long>(uint64_t(kStatSlots) * kStatStride);
     L.err = cv.take<unsigned int>(64);
     // the scratch region is shared by the step scratch and the init sort
@@ -98,6 +101,7 @@ StepArgs base_args(const sdm_ctx* x)
     a.scr_tmp = x->scr_tmp;
     a.scr_pos = x->scr_pos;
     a.scr_cnt = x->scr_cnt;
+    grid_args(x->grid, &a);
     return a;
 }
 
@@ -126,6 +130,7 @@ sdm_status upload_plan(sdm_ctx* x)
     if (!plan.block_cells.empty())
         SDM_HIP(hipMemcpyAsync(x->block_items, plan.block_cells.data(), plan.block_cells.size() * 4,
                                hipMemcpyHostToDevice, x->stream));
+    SDM_TRY(upload_grid(x->stream, plan, &x->grid));
     SDM_HIP(hipStreamSynchronize(x->stream));
     x->n_groups = static_cast<uint32_t>(ng);
     x->n_wave_cells = plan.wave_cells;
@@ -213,6 +218,7 @@ extern "C" sdm_status sdm_init(sdm_ctx** out, void* stream, void* workspace, siz
     x->group_begin = L.group_begin;
     x->group_end = L.group_end;
     x->block_items = L.block_items;
+    x->grid = L.grid;
     x->stats = L.stats;
     x->err = L.err;
     x->scr_kv = L.scr_kv;
@@ -329,7 +335,7 @@ extern "C" sdm_status sdm_get_plan(sdm_ctx* x, uint32_t* groups, uint32_t* wave_
     SDM_TRY(check_ctx(x));
     if (groups) *groups = x->n_groups;
     if (wave_cells) *wave_cells = x->n_wave_cells;
-    if (block_cells) *block_cells = x->n_block;
+    if (block_cells) *block_cells = x->n_block + x->grid.n_grid;
     return SDM_OK;
 }
 

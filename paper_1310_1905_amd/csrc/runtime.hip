@@ -144,8 +144,13 @@ void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_
                 plan.group_end.push_back(c);
                 open = false;
             }
-            plan.block_cells.push_back(c);
-            plan.block_sizes.push_back(n);
+            if (n > kGridMinSlots) {
+                plan.grid.push_back(GridCell{c, 0, 0, 0, 0, 0, 0, 0});
+                plan.grid_sizes.push_back(n);
+            } else {
+                plan.block_cells.push_back(c);
+                plan.block_sizes.push_back(n);
+            }
             continue;
         }
         if (open && (g_slots + n > group_slots || c - g_start >= static_cast<uint32_t>(kGroupMaxCells))) {
@@ -169,6 +174,21 @@ void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_
 
 void plan_finish(Plan& plan)
 {
+    // grid tier: bucket count 2^(floor(log2 N) - 1) <= N/2, chunk and tile tables
+    uint32_t tile = 0;
+    for (uint32_t i = 0; i < plan.grid.size(); ++i) {
+        const uint32_t n = plan.grid_sizes[i];
+        const uint32_t lg = 31u - static_cast<uint32_t>(__builtin_clz(n)) - 1u;
+        GridCell& gc = plan.grid[i];
+        gc.lg = lg;
+        gc.nb = 1u << lg;
+        gc.tile0 = tile;
+        gc.ntiles = (gc.nb + kGridTile - 1) / kGridTile;
+        for (uint32_t t = 0; t < gc.ntiles; ++t) plan.gtile.push_back(make_uint2(i, t * kGridTile));
+        tile += gc.ntiles;
+        for (uint32_t s0 = 0; s0 < n; s0 += kGridChunk) plan.gchunk.push_back(make_uint2(i, s0));
+        for (uint32_t y = 0; y < n / 2; y += kGridPairChunk) plan.gpchunk.push_back(make_uint2(i, y));
+    }
     // workgroup tier: largest cells first, so the long ones start early
     std::vector<uint32_t> idx(plan.block_cells.size());
     for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
@@ -191,6 +211,87 @@ bool shape_valid(const LaunchShape& c)
     const bool slots_ok = c.group_slots == 256 || c.group_slots == 512;
     return waves_ok && block_ok && slots_ok && c.groups_per_wave >= 1 && c.groups_per_wave <= 64 &&
            c.xcd_remap <= 1;
+}
+
+void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g)
+{
+    g->cap_cells = n_sd / (kGridMinSlots + 1) + 1;
+    g->cap_chunks = n_sd / kGridChunk + g->cap_cells;
+    g->cap_tiles = n_sd / 2 / kGridTile + g->cap_cells;
+    g->cap_pchunks = n_sd / 2 / kGridPairChunk + g->cap_cells;
+    g->gcell = c.take<GridCell>(g->cap_cells);
+    g->gchunk = c.take<uint2>(g->cap_chunks);
+    g->gtile = c.take<uint2>(g->cap_tiles);
+    g->gpchunk = c.take<uint2>(g->cap_pchunks);
+    g->gtilesum = c.take<uint32_t>(g->cap_tiles);
+}
+
+sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
+{
+    if (plan.grid.size() > g->cap_cells || plan.gchunk.size() > g->cap_chunks ||
+        plan.gtile.size() > g->cap_tiles || plan.gpchunk.size() > g->cap_pchunks) {
+        set_error("grid-tier tables exceed their capacity");
+        return SDM_ENOMEM;
+    }
+    if (!plan.grid.empty()) {
+        SDM_HIP(hipMemcpyAsync(g->gcell, plan.grid.data(), plan.grid.size() * sizeof(GridCell),
+                               hipMemcpyHostToDevice, s));
+        SDM_HIP(hipMemcpyAsync(g->gchunk, plan.gchunk.data(), plan.gchunk.size() * sizeof(uint2),
+                               hipMemcpyHostToDevice, s));
+        SDM_HIP(hipMemcpyAsync(g->gtile, plan.gtile.data(), plan.gtile.size() * sizeof(uint2),
+                               hipMemcpyHostToDevice, s));
+        SDM_HIP(hipMemcpyAsync(g->gpchunk, plan.gpchunk.data(), plan.gpchunk.size() * sizeof(uint2),
+                               hipMemcpyHostToDevice, s));
+    }
+    g->n_grid = static_cast<uint32_t>(plan.grid.size());
+    g->n_gchunk = static_cast<uint32_t>(plan.gchunk.size());
+    g->n_gtile = static_cast<uint32_t>(plan.gtile.size());
+    g->n_gpchunk = static_cast<uint32_t>(plan.gpchunk.size());
+    return SDM_OK;
+}
+
+void grid_args(const GridArrays& g, StepArgs* a)
+{
+    a->gcell = g.gcell;
+    a->n_grid = g.n_grid;
+    a->gchunk = g.gchunk;
+    a->n_gchunk = g.n_gchunk;
+    a->gtile = g.gtile;
+    a->n_gtile = g.n_gtile;
+    a->gpchunk = g.gpchunk;
+    a->n_gpchunk = g.n_gpchunk;
+    a->gtilesum = g.gtilesum;
+}
+
+template <bool BATCHED, bool PERM>
+static sdm_status launch_grid(hipStream_t s, const StepArgs& a)
+{
+    const dim3 blk(kGridBlock);
+    hipLaunchKernelGGL(k_grid_zero, dim3(a.n_gtile), blk, 0, s, a);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL((k_grid_keys<BATCHED>), dim3(a.n_gchunk), blk, 0, s, a);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL(k_grid_tile_sums, dim3(a.n_gtile), blk, 0, s, a);
+    SDM_LAUNCHED();
+    if (PERM) {
+        StepArgs b = a;
+        b.stats = nullptr;   // no counters from a permutation query
+        hipLaunchKernelGGL((k_grid_tile_offsets<false>), dim3((a.n_grid + kGridBlock - 1) / kGridBlock),
+                           blk, 0, s, b);
+    } else {
+        hipLaunchKernelGGL((k_grid_tile_offsets<BATCHED>),
+                           dim3((a.n_grid + kGridBlock - 1) / kGridBlock), blk, 0, s, a);
+    }
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL(k_grid_tile_scan, dim3(a.n_gtile), blk, 0, s, a);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL((k_grid_scatter<BATCHED>), dim3(a.n_gchunk), blk, 0, s, a);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL((k_grid_rank<BATCHED>), dim3(a.n_gchunk), blk, 0, s, a);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL((k_grid_pairs<BATCHED, PERM>), dim3(a.n_gpchunk), blk, 0, s, a);
+    SDM_LAUNCHED();
+    return SDM_OK;
 }
 
 // ------------------------------------------------------------ step launch
@@ -267,6 +368,10 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
                                   : launch_block<true, false>(s, a, n_block, shape));
         else SDM_TRY(perm ? launch_block<false, true>(s, a, n_block, shape)
                           : launch_block<false, false>(s, a, n_block, shape));
+    }
+    if (base.n_grid > 0) {
+        if (batched) SDM_TRY(perm ? launch_grid<true, true>(s, base) : launch_grid<true, false>(s, base));
+        else SDM_TRY(perm ? launch_grid<false, true>(s, base) : launch_grid<false, false>(s, base));
     }
     return SDM_OK;
 }

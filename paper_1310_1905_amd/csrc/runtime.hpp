@@ -125,7 +125,25 @@ struct LaunchShape {
 struct Plan {
     std::vector<uint32_t> group_begin, group_end, block_cells, block_sizes;
     uint32_t wave_cells = 0;
+    // grid tier
+    std::vector<GridCell> grid;
+    std::vector<uint32_t> grid_sizes;
+    std::vector<uint2> gchunk, gtile, gpchunk;
 };
+
+// Device arrays of the grid tier (inside a workspace) and their capacities.
+struct GridArrays {
+    GridCell* gcell = nullptr;
+    uint2* gchunk = nullptr;
+    uint2* gtile = nullptr;
+    uint2* gpchunk = nullptr;
+    uint32_t* gtilesum = nullptr;
+    uint64_t cap_cells = 0, cap_chunks = 0, cap_tiles = 0, cap_pchunks = 0;
+    uint32_t n_grid = 0, n_gchunk = 0, n_gtile = 0, n_gpchunk = 0;
+};
+void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g);
+sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g);
+void grid_args(const GridArrays& g, StepArgs* a);
 
 // Append to `plan` the cells [c_begin, c_end) whose storage-slot counts are
 // sizes[0..): cells above shape.group_slots go to the workgroup tier, the rest
@@ -135,7 +153,8 @@ void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_
                 uint32_t group_slots);
 void plan_finish(Plan& plan);
 
-// Enqueue the wave-tier and workgroup-tier kernels for one step.
+// Enqueue the wave-tier, workgroup-tier and grid-tier kernels for one step
+// (base carries the grid-tier arrays, see grid_args).
 sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* group_begin,
                        const uint32_t* group_end, uint32_t n_groups, const uint32_t* block_items,
                        uint32_t n_block, const LaunchShape& shape, bool batched, bool perm);

@@ -76,6 +76,29 @@ struct StepArgs {
     uint32_t* perm_out;
     uint32_t* nlive_out;
     uint32_t xcd_remap;
+    // grid tier (cells spread over many workgroups)
+    struct GridCell* gcell;
+    uint32_t n_grid;
+    const uint2* gchunk;          // (grid cell, first slot) per slot chunk
+    uint32_t n_gchunk;
+    const uint2* gtile;           // (grid cell, first bucket) per bucket tile
+    uint32_t n_gtile;
+    const uint2* gpchunk;         // (grid cell, first pair) per pair chunk
+    uint32_t n_gpchunk;
+    uint32_t* gtilesum;
+};
+
+// One cell of the grid tier.  lg and nb depend on the storage-slot count only
+// (any bucket count gives the same order); live and tile offsets are written
+// during the step.
+struct GridCell {
+    uint32_t cell;     // cell-table index
+    uint32_t lg;       // bucket bits
+    uint32_t nb;       // 2^lg buckets (<= N/2)
+    uint32_t tile0;    // first bucket tile
+    uint32_t ntiles;
+    uint32_t live;     // live SDs this step
+    uint32_t pad0, pad1;
 };
 
 // Resolved per-cell parameters.
@@ -230,20 +253,22 @@ struct alignas(16) GroupLds {
     uint32_t ucb[kGroupMaxCells];           // first uniform call of the cell
     CollEntry queue[kQueueCap];             // pending collisions (ring)
     union {
+        // entry CAP of kv / xi / r / slot, CAP/2 of pairinfo and the last
+        // ucall entry are write-only dummies that dead slots are sent to
         struct {
-            uint64_t kv[CAP];               // (key << 32 | slot) grouped by bucket
+            uint64_t kv[CAP + 2];           // (key << 32 | slot) grouped by bucket
+            uint32_t start[2 * CAP + 4];    // bucket counts, then bucket starts
             uint32_t keys[CAP];             // shuffle key of every group slot
-            uint32_t start[CAP + 4];        // bucket counts, then bucket starts
-            uint32_t slotinfo[CAP];         // cell | bucket base << 8 | lg << 24
+            uint32_t slotinfo[CAP];         // cell | bucket base << 8 | lg << 24 (base < 2048)
             uint32_t call[CAP / 4 + kGroupMaxCells];   // key call: slot base | cell << 9 | q << 15 | (words-1) << 22
         } sort;
         struct {
-            uint64_t xi[CAP];               // live SDs in sorted order
-            double r[CAP];
+            uint64_t xi[CAP + 2];           // live SDs in sorted order
+            double r[CAP + 2];
             double u[CAP / 2];              // uniform deviate of every pair
-            uint16_t slot[CAP];
-            uint16_t pairinfo[CAP / 2];     // sorted position of the first member | cell << 10
-            uint32_t ucall[CAP / 4 + kGroupMaxCells];   // first pair | cell << 9 | h << 15 | 2nd valid << 23
+            uint16_t slot[CAP + 2];
+            uint16_t pairinfo[CAP / 2 + 2]; // sorted position of the first member | cell << 10
+            uint32_t ucall[CAP / 4 + kGroupMaxCells + 1];   // first pair | cell << 9 | h << 15 | 2nd valid << 23
         } pairs;
     };
 };
@@ -406,19 +431,20 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
         const bool last_cell = lane + 1 == ncell;
         const uint32_t nl = has_cell ? ((last_cell ? n_tot : before_next) - before) : 0u;
         const uint32_t n_slots_l = has_cell ? ((last_cell ? G : first_next) - first) : 0u;
-        const uint32_t lgl = nl ? 31u - static_cast<uint32_t>(__clz(static_cast<int>(nl))) : 0u;
-        const uint32_t nbl = nl ? (1u << lgl) : 0u;               // 2^floor(log2 n) buckets
+        // 2^ceil(log2 n) buckets (at most one key per bucket on average)
+        const uint32_t lgl = nl > 1 ? 32u - static_cast<uint32_t>(__clz(static_cast<int>(nl - 1u))) : 0u;
+        const uint32_t nbl = nl ? (1u << lgl) : 0u;
         const uint32_t calls_l = (n_slots_l + 3u) >> 2;            // Philox calls for the keys
-        // one scan for bucket bases (bits 0..9), pair bases (10..19) and call bases (20..27)
-        const uint32_t packed = nbl | ((nl >> 1) << 10) | (calls_l << 20);
+        // one scan for bucket bases (bits 0..10), pair bases (11..19) and call bases (20..27)
+        const uint32_t packed = nbl | ((nl >> 1) << 11) | (calls_l << 20);
         const uint32_t incl = wave_inclusive_sum_dpp(packed);
         const uint32_t excl = incl - packed;
         const uint32_t tot = readlane_u32(incl, kWave - 1);
-        const uint32_t nb_tot = tot & 1023u;
-        const uint32_t q_tot = (tot >> 10) & 1023u;
+        const uint32_t nb_tot = tot & 2047u;
+        const uint32_t q_tot = (tot >> 11) & 511u;
         const uint32_t p_tot = tot >> 20;
-        const uint32_t b_base = excl & 1023u;
-        const uint32_t q_base = (excl >> 10) & 1023u;
+        const uint32_t b_base = excl & 2047u;
+        const uint32_t q_base = (excl >> 11) & 511u;
         const uint32_t p_base = excl >> 20;
         // uniform deviates: one Philox call per two pairs of a cell
         const uint32_t ucalls_l = ((nl >> 1) + 1u) >> 1;
@@ -480,7 +506,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
                 const uint32_t si = L.sort.slotinfo[s];
                 key[k] = L.sort.keys[s];
                 cid[k] = si & 255u;
-                bkt[k] = ((si >> 8) & 1023u) + bucket_of(key[k], si >> 24);
+                bkt[k] = ((si >> 8) & 2047u) + bucket_of(key[k], si >> 24);
                 arr[k] = atomicAdd(&L.sort.start[bkt[k]], 1u);
             }
         }
@@ -488,12 +514,12 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
 
         // exclusive scan of the nb_tot bucket counts; start[nb_tot] = n_tot
         {
-            const uint32_t per = (nb_tot + kWave - 1) / kWave;   // <= K
+            const uint32_t per = (nb_tot + kWave - 1) / kWave;   // <= 2K
             const uint32_t base = lane * per;
-            uint32_t v[K];
+            uint32_t v[2 * K];
             uint32_t sum = 0;
 #pragma unroll
-            for (int t = 0; t < K; ++t) {
+            for (int t = 0; t < 2 * K; ++t) {
                 v[t] = 0;
                 if (static_cast<uint32_t>(t) < per && base + t < nb_tot) v[t] = L.sort.start[base + t];
                 sum += v[t];
@@ -501,7 +527,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
             const uint32_t inc = wave_inclusive_sum_dpp(sum);
             uint32_t run = inc - sum;
 #pragma unroll
-            for (int t = 0; t < K; ++t) {
+            for (int t = 0; t < 2 * K; ++t) {
                 if (static_cast<uint32_t>(t) < per && base + t < nb_tot) L.sort.start[base + t] = run;
                 run += v[t];
             }
@@ -521,7 +547,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
         uint32_t pos[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            pos[k] = 0;
+            pos[k] = static_cast<uint32_t>(CAP);
             if (R.xv[k] != 0) {
                 const uint32_t lo = L.sort.start[bkt[k]];
                 const uint32_t hi = L.sort.start[bkt[k] + 1];
@@ -534,18 +560,18 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
         wave_sync();   // the sort arrays are overwritten below
 
         // (3) place the live SDs in sorted order; note the first member of each pair
+        if constexpr (!PERM) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (R.xv[k] != 0) {
-                const uint32_t s = lane + k * kWave;
-                const uint32_t p = pos[k];
-                const uint32_t eqn = L.eqn[cid[k]];
-                const uint32_t loc = p - (eqn & 1023u);
-                if constexpr (!PERM) {
+            for (int k = 0; k < K; ++k) {
+                if (R.xv[k] != 0) {
+                    const uint32_t s = lane + k * kWave;
+                    const uint32_t p = pos[k];
+                    const uint32_t eqn = L.eqn[cid[k]];
+                    const uint32_t loc = p - (eqn & 1023u);
+                    const uint32_t n_c = eqn >> 20;
                     L.pairs.xi[p] = R.xv[k];
                     L.pairs.r[p] = R.rv[k];
                     L.pairs.slot[p] = static_cast<uint16_t>(s);
-                    const uint32_t n_c = eqn >> 20;
                     if (!(loc & 1u) && loc + 1 < n_c) {
                         const uint32_t q = ((eqn >> 10) & 1023u) + (loc >> 1);
                         L.pairs.pairinfo[q] = static_cast<uint16_t>(p | (cid[k] << 10));
@@ -803,6 +829,200 @@ __global__ __launch_bounds__(BLOCK) void k_block_cells(const StepArgs a)
     if constexpr (!BATCHED && !PERM) {
         if (tid == 0 && (pair_acc || coll_acc))
             add_counts(a, false, 0, blockIdx.x, pair_acc, coll_acc);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grid tier: cells above kGridMinSlots storage slots, each spread over many
+// workgroups.  The step is a sequence of launches over all grid cells at once:
+// zero the bucket counters -> keys and bucket counts (global atomics) -> tile
+// sums -> per-cell scan of tile sums -> tile scans -> scatter -> in-bucket rank
+// -> pair tests.  Same algorithm and results as the other tiers.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kGridMinSlots = 16384;
+constexpr int kGridBlock = 256;
+constexpr uint32_t kGridChunk = 2048;     // slots per slot chunk (multiple of 4)
+constexpr uint32_t kGridTile = 4096;      // buckets per bucket tile
+constexpr uint32_t kGridPairChunk = 2048; // pairs per pair chunk
+
+static __global__ __launch_bounds__(kGridBlock) void k_grid_zero(const StepArgs a)
+{
+    const uint2 t = a.gtile[blockIdx.x];
+    GridCell& gc = a.gcell[t.x];
+    const uint32_t off = a.off_begin[gc.cell];
+    const uint32_t end = min(t.y + kGridTile, gc.nb + 1);   // includes the sentinel slot
+    for (uint32_t b = t.y + threadIdx.x; b < end; b += kGridBlock) a.scr_cnt[off + b] = 0;
+    if (t.y == 0 && threadIdx.x == 0) gc.live = 0;
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(kGridBlock) void k_grid_keys(const StepArgs a)
+{
+    __shared__ uint32_t s_red[kGridBlock / kWave];
+    const uint2 ch = a.gchunk[blockIdx.x];
+    GridCell& gc = a.gcell[ch.x];
+    const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
+    const uint32_t lg = gc.lg;
+    const uint32_t q_end = min(ch.y + kGridChunk, j.n_slots + 3u) / 4u;
+    uint32_t live = 0;
+    for (uint32_t q = ch.y / 4u + threadIdx.x; q < q_end; q += kGridBlock) {
+        const Words4 w = philox4x32_10(q, j.rng_cell, j.step, kTagShuffle, j.k0, j.k1);
+#pragma unroll
+        for (uint32_t t = 0; t < 4; ++t) {
+            const uint32_t s = 4 * q + t;
+            if (s < j.n_slots && a.xi[j.off + s] != 0) {
+                const uint32_t arr = atomicAdd(&a.scr_cnt[j.off + bucket_of(w.w[t], lg)], 1u);
+                a.scr_tmp[j.off + s] = (static_cast<uint64_t>(w.w[t]) << 32) | arr;
+                ++live;
+            }
+        }
+    }
+    const uint32_t tot = block_sum<kGridBlock>(live, s_red);
+    if (threadIdx.x == 0 && tot) atomicAdd(&gc.live, tot);
+}
+
+static __global__ __launch_bounds__(kGridBlock) void k_grid_tile_sums(const StepArgs a)
+{
+    __shared__ uint32_t s_red[kGridBlock / kWave];
+    const uint2 t = a.gtile[blockIdx.x];
+    const GridCell& gc = a.gcell[t.x];
+    const uint32_t off = a.off_begin[gc.cell];
+    const uint32_t end = min(t.y + kGridTile, gc.nb);
+    uint32_t sum = 0;
+    for (uint32_t b = t.y + threadIdx.x; b < end; b += kGridBlock) sum += a.scr_cnt[off + b];
+    const uint32_t tot = block_sum<kGridBlock>(sum, s_red);
+    if (threadIdx.x == 0) a.gtilesum[blockIdx.x] = tot;
+}
+
+// one thread per grid cell: exclusive scan of its tile sums; sentinel = live count
+template <bool BATCHED>
+__global__ __launch_bounds__(kGridBlock) void k_grid_tile_offsets(const StepArgs a)
+{
+    for (uint32_t i = blockIdx.x * kGridBlock + threadIdx.x; i < a.n_grid; i += gridDim.x * kGridBlock) {
+        const GridCell& gc = a.gcell[i];
+        uint32_t run = 0;
+        for (uint32_t t = 0; t < gc.ntiles; ++t) {
+            const uint32_t v = a.gtilesum[gc.tile0 + t];
+            a.gtilesum[gc.tile0 + t] = run;
+            run += v;
+        }
+        a.scr_cnt[a.off_begin[gc.cell] + gc.nb] = run;
+        const unsigned long long pairs = run >> 1;
+        if constexpr (BATCHED) {
+            if (pairs) atomicAdd(&a.inst[a.cell_inst[gc.cell]].pair_tests, pairs);
+        } else {
+            if (pairs && a.stats) atomicAdd(a.stats + (i % kStatSlots) * kStatStride, pairs);
+        }
+    }
+}
+
+static __global__ __launch_bounds__(kGridBlock) void k_grid_tile_scan(const StepArgs a)
+{
+    __shared__ uint32_t s_red[kGridBlock / kWave];
+    constexpr int W = kGridBlock / kWave;
+    const uint2 t = a.gtile[blockIdx.x];
+    const GridCell& gc = a.gcell[t.x];
+    const uint32_t off = a.off_begin[gc.cell];
+    const uint32_t end = min(t.y + kGridTile, gc.nb);
+    const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    uint32_t carry = a.gtilesum[blockIdx.x];
+    for (uint32_t base = t.y; base < end; base += kGridBlock) {
+        const uint32_t b = base + threadIdx.x;
+        const uint32_t v = b < end ? a.scr_cnt[off + b] : 0u;
+        const uint32_t incl_w = wave_inclusive_sum(v, lane);
+        if (lane == kWave - 1) s_red[wv] = incl_w;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint32_t x = s_red[w];
+            before += (static_cast<uint32_t>(w) < wv) ? x : 0u;
+            total += x;
+        }
+        if (b < end) a.scr_cnt[off + b] = carry + before + incl_w - v;
+        carry += total;
+        __syncthreads();
+    }
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(kGridBlock) void k_grid_scatter(const StepArgs a)
+{
+    const uint2 ch = a.gchunk[blockIdx.x];
+    const GridCell& gc = a.gcell[ch.x];
+    const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
+    const uint32_t end = min(ch.y + kGridChunk, j.n_slots);
+    for (uint32_t s = ch.y + threadIdx.x; s < end; s += kGridBlock) {
+        if (a.xi[j.off + s] != 0) {
+            const uint64_t t = a.scr_tmp[j.off + s];
+            const uint32_t key = static_cast<uint32_t>(t >> 32);
+            const uint32_t p = a.scr_cnt[j.off + bucket_of(key, gc.lg)] + static_cast<uint32_t>(t);
+            a.scr_kv[j.off + p] = (static_cast<uint64_t>(key) << 32) | s;
+        }
+    }
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(kGridBlock) void k_grid_rank(const StepArgs a)
+{
+    const uint2 ch = a.gchunk[blockIdx.x];
+    const GridCell& gc = a.gcell[ch.x];
+    const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
+    const uint32_t end = min(ch.y + kGridChunk, j.n_slots);
+    for (uint32_t s = ch.y + threadIdx.x; s < end; s += kGridBlock) {
+        if (a.xi[j.off + s] != 0) {
+            const uint32_t key = static_cast<uint32_t>(a.scr_tmp[j.off + s] >> 32);
+            const uint32_t b = bucket_of(key, gc.lg);
+            const uint32_t lo = a.scr_cnt[j.off + b], hi = a.scr_cnt[j.off + b + 1];
+            const uint64_t me = (static_cast<uint64_t>(key) << 32) | s;
+            uint32_t rank = 0;
+            for (uint32_t e = lo; e < hi; ++e) rank += (a.scr_kv[j.off + e] < me) ? 1u : 0u;
+            a.scr_pos[j.off + lo + rank] = s;
+        }
+    }
+}
+
+// pair tests: each thread takes the two pairs of one uniform call
+template <bool BATCHED, bool PERM>
+__global__ __launch_bounds__(kGridBlock) void k_grid_pairs(const StepArgs a)
+{
+    __shared__ uint32_t s_red[kGridBlock / kWave];
+    const uint2 ch = a.gpchunk[blockIdx.x];
+    const GridCell& gc = a.gcell[ch.x];
+    const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
+    const uint32_t n = gc.live;
+    if constexpr (PERM) {
+        // copy the sorted order of this chunk's pair range (both members) out
+        const uint32_t lo = 2 * ch.y;
+        const uint32_t hi = min(2 * (ch.y + kGridPairChunk), n);
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += kGridBlock) a.perm_out[j.off + i] = a.scr_pos[j.off + i];
+        if (ch.y == 0 && threadIdx.x == 0) {
+            a.nlive_out[gc.cell] = n;
+            if (n & 1u) a.perm_out[j.off + n - 1] = a.scr_pos[j.off + n - 1];
+        }
+        return;
+    }
+    const uint32_t npairs = n >> 1;
+    const double scale = npairs ? upscale_factor(n) : 0.0;
+    uint32_t coll = 0;
+    const uint32_t h_end = (min(ch.y + kGridPairChunk, npairs) + 1u) / 2u;
+    for (uint32_t h = ch.y / 2u + threadIdx.x; h < h_end; h += kGridBlock) {
+        const Words4 w = philox4x32_10(h, j.rng_cell, j.step, kTagUniform, j.k0, j.k1);
+#pragma unroll
+        for (uint32_t t = 0; t < 2; ++t) {
+            const uint32_t m = 2 * h + t;
+            if (m >= npairs) break;
+            const double u = t ? uniform_open01(w.w[2], w.w[3]) : uniform_open01(w.w[0], w.w[1]);
+            const uint32_t sa = a.scr_pos[j.off + 2 * m], sb = a.scr_pos[j.off + 2 * m + 1];
+            const uint64_t xa = a.xi[j.off + sa], xb = a.xi[j.off + sb];
+            const double ra = a.r[j.off + sa], rb = a.r[j.off + sb];
+            if (collide_pair_global(a, j, scale, u, sa, sb, xa, xb, ra, rb)) ++coll;
+        }
+    }
+    const uint32_t tot = block_sum<kGridBlock>(coll, s_red);
+    if (threadIdx.x == 0 && tot) {
+        if constexpr (BATCHED) atomicAdd(&a.inst[j.inst].collisions, static_cast<unsigned long long>(tot));
+        else atomicAdd(a.stats + (blockIdx.x % kStatSlots) * kStatStride + 1, static_cast<unsigned long long>(tot));
     }
 }
 

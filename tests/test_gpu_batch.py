@@ -20,6 +20,8 @@ def _oracle_run(oracle_mod, pop, steps, first_step=0):
 def _mixed_instances(n, seed):
     pops = synth.ensemble(seed=seed, n_instances=n, log2_lo=3, log2_hi=11)
     # and a few multi-cell columns with ragged cells of both tiers
+    big = synth.box_golovin(seed=seed, n_sd=40000, dV=1e3)
+    pops.append(big)
     for i in range(3):
         p = synth.tiny_cells(seed=seed + i, n_cells=20, max_per_cell=500, xi_max=80)
         p.dV = p.dV * 1e-4
@@ -62,7 +64,7 @@ def test_graph_replays_with_admission_in_between(sdm_mod, oracle_mod):
     """Instances join and leave between replays; each one's result equals its own
     oracle run over the steps it was present for."""
     pops = _mixed_instances(10, seed=5)
-    b = sdm_mod.Batch(max_sd=200000, max_cells=400, max_instances=16)
+    b = sdm_mod.Batch(max_sd=300000, max_cells=400, max_instances=16)
     live = {}
     done = []
     plan = {0: [0, 1, 2, 3], 3: [4, 5], 6: [6, 7, 8], 9: [9, 10, 11, 12]}

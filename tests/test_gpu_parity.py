@@ -100,6 +100,24 @@ def test_many_cells_per_group(sdm_mod, oracle_mod):
     assert wave_cells == pop.n_cells and block_cells == 0 and groups <= pop.n_cells // 64 + 60
 
 
+@pytest.mark.parametrize("kernel", ["geometric", "golovin"])
+def test_grid_tier_cells(sdm_mod, oracle_mod, kernel):
+    """Cells above 16384 storage slots run spread over many workgroups."""
+    pop = synth.tiny_cells(seed=91, n_cells=6, max_per_cell=60000, xi_max=30, dead_fraction=0.2)
+    sizes = np.bincount(pop.cell, minlength=pop.n_cells)
+    assert (sizes > 16384).sum() >= 3
+    ctx, ref = _run_pair(sdm_mod, oracle_mod, pop, 4, 3.0, kernel, dV_scale=1e-6, threads=6)
+    _assert_same(ctx, ref, f"grid tier {kernel}")
+    assert ref.stats[1] > 0
+    order, nlive = ctx.permutation(seed=17, step=3)
+    order, nlive = order.cpu().numpy(), nlive.cpu().numpy()
+    off = ref.offsets.astype(np.int64)
+    for c in range(ref.n_cells):
+        exp = oracle_mod.cell_order(ref.xi[off[c]:off[c + 1]], 17, c, 3)
+        assert nlive[c] == exp.size
+        assert np.array_equal(order[off[c]:off[c] + exp.size], exp), c
+
+
 def test_empty_and_degenerate_inputs(sdm_mod, oracle_mod):
     # no SDs at all, a single cell with one SD, and a cell with only dead SDs
     ctx = sdm_mod.Context(np.zeros(0, np.uint32), np.zeros(0, np.uint64), np.zeros(0),
