@@ -89,7 +89,7 @@ def lib() -> ctypes.CDLL:
     L.oracle_moment_cell.restype = dbl
     L.oracle_sd_conc.argtypes = [u32, P, P, P]
     L.oracle_sd_conc.restype = None
-    L.oracle_max_probability.argtypes = [u32, P, P, P, P, dbl, i32, P, u64, u32, u32]
+    L.oracle_max_probability.argtypes = [u32, P, P, P, P, dbl, i32, P, u64, u32, u32, P]
     L.oracle_max_probability.restype = dbl
     _lib = L
     return L
@@ -244,11 +244,15 @@ class SlotState:
         lib().oracle_sd_conc(self.n_cells, _ptr(self.offsets), _ptr(self.xi), _ptr(out))
         return out
 
-    def max_probability(self, dt, kind, seed, step, params=None):
+    def max_probability(self, dt, kind, seed, step, params=None, per_cell: bool = False):
+        """Largest P_ij over the pairs ``step`` would test; with ``per_cell`` also
+        the per-cell maxima.  The state is not changed."""
         p = _params(params)
-        return float(lib().oracle_max_probability(self.n_cells, _ptr(self.offsets), _ptr(self.dV),
-                                                  _ptr(self.xi), _ptr(self.r), dt, kind, _ptr(p),
-                                                  seed, step, 0))
+        cm = np.zeros(max(1, self.n_cells))
+        g = float(lib().oracle_max_probability(self.n_cells, _ptr(self.offsets), _ptr(self.dV),
+                                               _ptr(self.xi), _ptr(self.r), dt, kind, _ptr(p),
+                                               seed, step, 0, _ptr(cm)))
+        return (g, cm[:self.n_cells].copy()) if per_cell else g
 
     def input_order(self):
         """(xi, r) scattered back to input order."""

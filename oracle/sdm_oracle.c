@@ -484,11 +484,12 @@ void oracle_sd_conc(uint32_t n_cells, const uint64_t *offsets, const uint64_t *x
 
 /* Largest collision probability over the pairs one step would test (the
  * quantity an adaptive sub-step would be chosen from); the state is not
- * changed. */
+ * changed.  cell_max (optional) receives the largest value of each cell, 0 for
+ * a cell with fewer than two live super-droplets. */
 double oracle_max_probability(uint32_t n_cells, const uint64_t *offsets, const double *dV,
                               const uint64_t *xi, const double *r, double dt, int kernel,
                               const double *params, uint64_t seed, uint32_t step,
-                              uint32_t cell_index_base)
+                              uint32_t cell_index_base, double *cell_max)
 {
     double pmax = 0.0;
     uint32_t max_slots = 0;
@@ -501,15 +502,19 @@ double oracle_max_probability(uint32_t n_cells, const uint64_t *offsets, const d
         uint64_t base = offsets[c];
         uint32_t n = oracle_cell_order((uint32_t)(offsets[c + 1] - base), xi + base, seed,
                                        cell_index_base + c, step, order);
-        if (n < 2) continue;
-        double scale = oracle_upscale(n);
-        for (uint32_t m = 0; m < n / 2u; ++m) {
-            uint64_t a = base + order[2u * m], b = base + order[2u * m + 1u];
-            uint64_t xj = xi[a] >= xi[b] ? xi[a] : xi[b];
-            double K = oracle_kernel(kernel, params, r[a], r[b]);
-            double p = oracle_probability(xj, K, dt, dV[c], scale);
-            if (p > pmax) pmax = p;
+        double cmax = 0.0;
+        if (n >= 2) {
+            double scale = oracle_upscale(n);
+            for (uint32_t m = 0; m < n / 2u; ++m) {
+                uint64_t a = base + order[2u * m], b = base + order[2u * m + 1u];
+                uint64_t xj = xi[a] >= xi[b] ? xi[a] : xi[b];
+                double K = oracle_kernel(kernel, params, r[a], r[b]);
+                double p = oracle_probability(xj, K, dt, dV[c], scale);
+                if (p > cmax) cmax = p;
+            }
         }
+        if (cell_max) cell_max[c] = cmax;
+        if (cmax > pmax) pmax = cmax;
     }
     free(order);
     return pmax;

@@ -149,3 +149,21 @@ def test_third_moment_conserved_over_golovin_run(oracle_mod):
     assert st.moments(3)[0] == pytest.approx(m3_0, rel=1e-12)
     assert st.moments(0)[0] < m0_0
     assert st.sd_conc()[0] == np.count_nonzero(st.xi)
+
+
+def test_probe_per_cell_maxima(oracle_mod):
+    """Per-cell maxima by brute force over each cell's pairing; 0 below two live SDs."""
+    pop, st = _state(oracle_mod, seed=17, n_cells=6, max_per_cell=50)
+    seed, step, dt = 5, 2, 1.3
+    g, cm = st.max_probability(dt, oracle_mod.GOLOVIN, seed, step, per_cell=True)
+    assert g == cm.max()
+    for c, (b, e) in enumerate(_cells(st)):
+        order = oracle_mod.cell_order(st.xi[b:e], seed, c, step)
+        n = len(order)
+        best = 0.0
+        for m in range(n // 2):
+            ia, ib = b + int(order[2 * m]), b + int(order[2 * m + 1])
+            xj = max(int(st.xi[ia]), int(st.xi[ib]))
+            K = oracle_mod.kernel(oracle_mod.GOLOVIN, float(st.r[ia]), float(st.r[ib]))
+            best = max(best, xj * K * dt / st.dV[c] * (n * (n - 1) / 2) / (n // 2))
+        assert cm[c] == pytest.approx(best, rel=1e-14, abs=0.0)
