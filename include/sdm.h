@@ -148,6 +148,64 @@ sdm_status sdm_get_layout(sdm_ctx *ctx, const uint32_t **offsets, const uint32_t
 sdm_status sdm_debug_permutation(sdm_ctx *ctx, uint64_t seed, uint64_t step,
                                  uint32_t *order_out, uint32_t *n_live_out);
 
+/* ------------------------------------------------------------------------ */
+/* Gridded diagnostics (Sect. 5.2, the particle-based scheme's diagnostics:  */
+/* super-droplet concentration and k-th radius moment per cell).  Both are   */
+/* enqueued on the context stream and do not synchronise it.                 */
+/* ------------------------------------------------------------------------ */
+
+/* out[c] (dev uint32[n_cells]) = number of super-droplets with xi > 0 in c.
+ * Errors: SDM_EINVAL (out NULL while n_cells > 0), SDM_EDEVICE. */
+sdm_status sdm_diag_sd_conc(sdm_ctx *ctx, uint32_t *out);
+
+/* out[c] (dev double[n_cells]) = (rho_d[c] dV[c])^-1 * sum of xi_i r_i^k over
+ * the super-droplets of cell c with xi_i > 0 and r_min <= r_i <= r_max
+ * (a closed range; r_min > r_max gives zeros).  rho_d (dev double[n_cells])
+ * is the dry-air density; NULL means 1, i.e. moments per unit volume.
+ * r_i^k is the product of k factors r_i taken left to right (k <= 16); the
+ * sum runs in a fixed order: 64 partial sums, partial l taking the cell's
+ * local slots l, l+64, ... in ascending order, then folded pairwise
+ * (partial[l] += partial[l+d], d = 32, 16, ..., 1), so the result is
+ * reproducible bit for bit.
+ * Errors: SDM_EINVAL (k > 16, NaN bound, out NULL), SDM_EDEVICE. */
+sdm_status sdm_diag_moments(sdm_ctx *ctx, uint32_t k, double r_min, double r_max,
+                            const double *rho_d, double *out);
+
+/* ------------------------------------------------------------------------ */
+/* Collision-probability probe and sub-stepping (the coalescence sub-steps   */
+/* of Sect. 5.1.4, with P_ij driving their number as the paper proposes).   */
+/* ------------------------------------------------------------------------ */
+
+/* Evaluate eq. (P_ij) for every pair that sdm_coalesce_step(ctx, dt, kernel,
+ * seed, step) would test, without changing the state: cell_max (dev
+ * double[n_cells], nullable) gets each cell's largest P_ij (0 for a cell with
+ * fewer than two live super-droplets), *max_out (host, nullable) the largest
+ * over all cells, in which case the stream is synchronised.
+ * Errors: as sdm_coalesce_step. */
+sdm_status sdm_probe_probability(sdm_ctx *ctx, double dt, sdm_kernel kernel, uint64_t seed,
+                                 uint64_t step, double *cell_max, double *max_out);
+
+/* n_substeps coalescence steps of length dt / n_substeps (dt divided once, in
+ * binary64), with step counters first_step .. first_step + n_substeps - 1.
+ * Identical to calling sdm_coalesce_step that many times.
+ * Errors: SDM_EINVAL (n_substeps == 0, a counter >= 2^32, or as
+ * sdm_coalesce_step). */
+sdm_status sdm_coalesce_substeps(sdm_ctx *ctx, double dt, uint32_t n_substeps, sdm_kernel kernel,
+                                 uint64_t seed, uint64_t first_step);
+
+/* Adaptive sub-stepping: probe step first_step with the full dt, take
+ * n = ceil(pmax / p_limit) sub-steps (1 if pmax <= p_limit, at most
+ * max_substeps) and run sdm_coalesce_substeps(ctx, dt, n, kernel, seed,
+ * first_step).  The first sub-step uses the probed pairing, so its largest
+ * P_ij is pmax / n up to rounding; later sub-steps draw new pairings.
+ * *substeps_out (host, nullable) = n; the caller advances its step counter by
+ * n.  Synchronises the stream once (to read pmax).
+ * Errors: SDM_EINVAL (p_limit not finite and > 0, max_substeps == 0, or as
+ * sdm_coalesce_substeps). */
+sdm_status sdm_coalesce_adaptive(sdm_ctx *ctx, double dt, double p_limit, uint32_t max_substeps,
+                                 sdm_kernel kernel, uint64_t seed, uint64_t first_step,
+                                 uint32_t *substeps_out);
+
 /* Launch plan of a context: number of wave-tier groups (runs of consecutive
  * cells processed by one wavefront), cells in them, and cells handled one
  * workgroup per cell (cells with more storage slots than a group holds).

@@ -1,9 +1,11 @@
 // context.hip -- the single-run C ABI: sdm_init / sdm_coalesce_step and the
 // state, counter, layout, plan and permutation queries of a context.
 #include "runtime.hpp"
+#include "diag_kernels.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 using namespace sdm;
 
@@ -24,6 +26,9 @@ struct sdm_ctx {
     GridArrays grid;
     unsigned long long* stats = nullptr;
     unsigned int* err = nullptr;
+    uint32_t* probe_order = nullptr;
+    uint32_t* probe_nlive = nullptr;
+    unsigned long long* probe_max = nullptr;
     uint64_t* scr_kv = nullptr;
     uint64_t* scr_tmp = nullptr;
     uint32_t* scr_pos = nullptr;
@@ -48,6 +53,10 @@ struct CtxLayout {
     GridArrays grid;
     unsigned long long* stats;
     unsigned int* err;
+    // probe: pairing order, live counts and the running maximum of P_ij
+    uint32_t* probe_order;
+    uint32_t* probe_nlive;
+    unsigned long long* probe_max;
     // scratch (workgroup-tier sort arrays during steps; sort-by-cell arrays during init)
     uint64_t* scr_kv;
     uint64_t* scr_tmp;
@@ -72,6 +81,9 @@ CtxLayout layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t c)
     carve_grid(cv, n, &L.grid);
     L.stats = cv.take<unsigned long long>(uint64_t(kStatSlots) * kStatStride);
     L.err = cv.take<unsigned int>(64);
+    L.probe_order = cv.take<uint32_t>(n);
+    L.probe_nlive = cv.take<uint32_t>(c);
+    L.probe_max = cv.take<unsigned long long>(32);
     // the scratch region is shared by the step scratch and the init sort
     const uintptr_t scratch_begin = cv.cur;
     L.scr_kv = cv.take<uint64_t>(n);
@@ -221,6 +233,9 @@ extern "C" sdm_status sdm_init(sdm_ctx** out, void* stream, void* workspace, siz
     x->grid = L.grid;
     x->stats = L.stats;
     x->err = L.err;
+    x->probe_order = L.probe_order;
+    x->probe_nlive = L.probe_nlive;
+    x->probe_max = L.probe_max;
     x->scr_kv = L.scr_kv;
     x->scr_tmp = L.scr_tmp;
     x->scr_pos = L.scr_pos;
@@ -288,6 +303,144 @@ extern "C" sdm_status sdm_debug_permutation(sdm_ctx* x, uint64_t seed, uint64_t 
     a.nlive_out = n_live_out;
     SDM_TRY(launch(x, a, true));
     SDM_HIP(hipStreamSynchronize(x->stream));
+    return SDM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics, probability probe and sub-stepping
+// ---------------------------------------------------------------------------
+// Number of equal sub-steps that brings the probed largest P_ij down to
+// p_limit: ceil(pmax / p_limit), at least 1 and at most max_substeps.
+static uint32_t substep_count(double pmax, double p_limit, uint32_t max_substeps)
+{
+    if (!(pmax > p_limit)) return 1;
+    const double q = std::ceil(pmax / p_limit);
+    return q >= static_cast<double>(max_substeps) ? max_substeps : static_cast<uint32_t>(q);
+}
+
+static uint32_t diag_grid(uint32_t n_cells)
+{
+    return grid_for(n_cells, kDiagCellsPerBlock, 1u << 16);
+}
+
+extern "C" sdm_status sdm_diag_sd_conc(sdm_ctx* x, uint32_t* out)
+{
+    SDM_TRY(check_ctx(x));
+    if (x->n_cells == 0) return SDM_OK;
+    if (!out) {
+        set_error("out must be non-NULL");
+        return SDM_EINVAL;
+    }
+    hipLaunchKernelGGL(k_sd_conc, dim3(diag_grid(x->n_cells)), dim3(kDiagBlock), 0, x->stream,
+                       x->offsets, x->xi, x->n_cells, out);
+    SDM_LAUNCHED();
+    return SDM_OK;
+}
+
+extern "C" sdm_status sdm_diag_moments(sdm_ctx* x, uint32_t k, double r_min, double r_max,
+                                       const double* rho_d, double* out)
+{
+    SDM_TRY(check_ctx(x));
+    if (k > kMaxMomentOrder) {
+        set_error("moment order %u above %u", k, kMaxMomentOrder);
+        return SDM_EINVAL;
+    }
+    if (std::isnan(r_min) || std::isnan(r_max)) {
+        set_error("radius range bounds must not be NaN");
+        return SDM_EINVAL;
+    }
+    if (x->n_cells == 0) return SDM_OK;
+    if (!out) {
+        set_error("out must be non-NULL");
+        return SDM_EINVAL;
+    }
+    hipLaunchKernelGGL(k_moments, dim3(diag_grid(x->n_cells)), dim3(kDiagBlock), 0, x->stream,
+                       x->offsets, x->dV, x->xi, x->r, x->n_cells, k, r_min, r_max, rho_d, out);
+    SDM_LAUNCHED();
+    return SDM_OK;
+}
+
+// Enqueue the probe of step `step`; the maximum lands in x->probe_max.
+static sdm_status enqueue_probe(sdm_ctx* x, double dt, sdm_kernel kernel, uint64_t seed,
+                                uint64_t step, double* cell_max)
+{
+    StepArgs a;
+    SDM_TRY(step_args(x, dt, kernel, seed, step, &a));
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, x->stream, x->probe_max, uint64_t(1),
+                       0ull);
+    SDM_LAUNCHED();
+    if (x->n_cells == 0) return SDM_OK;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(x->n_cells, 256, 4096)), dim3(256), 0,
+                       x->stream, x->probe_nlive, uint64_t(x->n_cells), 0u);
+    SDM_LAUNCHED();
+    a.perm_out = x->probe_order;
+    a.nlive_out = x->probe_nlive;
+    SDM_TRY(launch(x, a, true));
+    hipLaunchKernelGGL(k_probe_pairs, dim3(diag_grid(x->n_cells)), dim3(kDiagBlock), 0, x->stream,
+                       x->offsets, x->dV, x->xi, x->r, x->probe_order, x->probe_nlive, x->n_cells,
+                       static_cast<uint32_t>(kernel), a.kp, dt, cell_max, x->probe_max);
+    SDM_LAUNCHED();
+    return SDM_OK;
+}
+
+static sdm_status read_probe_max(sdm_ctx* x, double* out)
+{
+    unsigned long long bits = 0;
+    SDM_HIP(hipMemcpyAsync(&bits, x->probe_max, sizeof(bits), hipMemcpyDeviceToHost, x->stream));
+    SDM_HIP(hipStreamSynchronize(x->stream));
+    double v;
+    std::memcpy(&v, &bits, sizeof(v));
+    *out = v;
+    return SDM_OK;
+}
+
+extern "C" sdm_status sdm_probe_probability(sdm_ctx* x, double dt, sdm_kernel kernel,
+                                            uint64_t seed, uint64_t step, double* cell_max,
+                                            double* max_out)
+{
+    SDM_TRY(check_ctx(x));
+    SDM_TRY(enqueue_probe(x, dt, kernel, seed, step, cell_max));
+    if (max_out) SDM_TRY(read_probe_max(x, max_out));
+    return SDM_OK;
+}
+
+extern "C" sdm_status sdm_coalesce_substeps(sdm_ctx* x, double dt, uint32_t n_substeps,
+                                            sdm_kernel kernel, uint64_t seed, uint64_t first_step)
+{
+    SDM_TRY(check_ctx(x));
+    if (n_substeps == 0) {
+        set_error("n_substeps must be >= 1");
+        return SDM_EINVAL;
+    }
+    if (first_step + n_substeps > (1ull << 32) || first_step >= (1ull << 32)) {
+        set_error("step counters must stay below 2^32");
+        return SDM_EINVAL;
+    }
+    const double h = dt / static_cast<double>(n_substeps);
+    for (uint32_t i = 0; i < n_substeps; ++i) {
+        StepArgs a;
+        SDM_TRY(step_args(x, h, kernel, seed, first_step + i, &a));
+        SDM_TRY(launch(x, a, false));
+    }
+    return SDM_OK;
+}
+
+extern "C" sdm_status sdm_coalesce_adaptive(sdm_ctx* x, double dt, double p_limit,
+                                            uint32_t max_substeps, sdm_kernel kernel,
+                                            uint64_t seed, uint64_t first_step,
+                                            uint32_t* substeps_out)
+{
+    SDM_TRY(check_ctx(x));
+    if (!(p_limit > 0.0) || !std::isfinite(p_limit) || max_substeps == 0) {
+        set_error("p_limit must be finite and > 0 and max_substeps >= 1");
+        return SDM_EINVAL;
+    }
+    double pmax = 0.0;
+    SDM_TRY(enqueue_probe(x, dt, kernel, seed, first_step, nullptr));
+    SDM_TRY(read_probe_max(x, &pmax));
+    const uint32_t n = substep_count(pmax, p_limit, max_substeps);
+    SDM_TRY(sdm_coalesce_substeps(x, dt, n, kernel, seed, first_step));
+    if (substeps_out) *substeps_out = n;
     return SDM_OK;
 }
 

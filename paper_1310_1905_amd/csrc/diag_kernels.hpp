@@ -1,0 +1,127 @@
+// diag_kernels.hpp -- gridded diagnostics of the particle-based scheme
+// (Sect. 5.2: super-droplet concentration and radius moments per cell) and the
+// collision-probability probe (largest P_ij of eq. (P_ij) over the pairs of a
+// step), as segmented reductions over the cell-sorted storage.
+//
+// One wavefront per cell.  Lane l accumulates the cell's local slots
+// l, l+64, l+128, ... in ascending order; the 64 partial sums are then folded
+// pairwise, partial[l] += partial[l+d] for d = 32, 16, ..., 1.  This order is
+// part of the definition of the result, so moments are reproducible bit for bit
+// whatever the launch shape.
+#pragma once
+
+#include "device_math.hpp"
+
+#pragma clang fp contract(off)
+
+namespace sdm {
+namespace {
+
+constexpr int kDiagBlock = 256;
+constexpr uint32_t kMaxMomentOrder = 16;
+constexpr uint32_t kDiagCellsPerBlock = kDiagBlock / 64;
+
+__device__ __forceinline__ double wave_fold_sum(double v, uint32_t lane)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const double o = __shfl_down(v, d, 64);
+        if (lane < static_cast<uint32_t>(d)) v = v + o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// out[c] = (rho_d[c] dV[c])^-1 sum_{live i in c, r_min <= r_i <= r_max} xi_i r_i^k
+__global__ __launch_bounds__(kDiagBlock) void k_moments(const uint32_t* __restrict__ off,
+                                                        const double* __restrict__ dV,
+                                                        const uint64_t* __restrict__ xi,
+                                                        const double* __restrict__ r,
+                                                        uint32_t n_cells, uint32_t k, double r_min,
+                                                        double r_max,
+                                                        const double* __restrict__ rho_d,
+                                                        double* __restrict__ out)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kDiagCellsPerBlock;
+    for (uint64_t c = static_cast<uint64_t>(blockIdx.x) * kDiagCellsPerBlock + threadIdx.x / 64u;
+         c < n_cells; c += stride) {
+        const uint32_t b = off[c], n = off[c + 1] - b;
+        double acc = 0.0;
+        for (uint32_t i = lane; i < n; i += 64u) {
+            const uint64_t x = xi[b + i];
+            const double ri = r[b + i];
+            if (x != 0 && ri >= r_min && ri <= r_max) {
+                double rk = 1.0;
+                for (uint32_t e = 0; e < k; ++e) rk = rk * ri;
+                acc = acc + static_cast<double>(x) * rk;
+            }
+        }
+        acc = wave_fold_sum(acc, lane);
+        if (lane == 0) out[c] = acc / ((rho_d ? rho_d[c] : 1.0) * dV[c]);
+    }
+}
+
+// out[c] = number of live super-droplets of cell c
+__global__ __launch_bounds__(kDiagBlock) void k_sd_conc(const uint32_t* __restrict__ off,
+                                                        const uint64_t* __restrict__ xi,
+                                                        uint32_t n_cells, uint32_t* __restrict__ out)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kDiagCellsPerBlock;
+    for (uint64_t c = static_cast<uint64_t>(blockIdx.x) * kDiagCellsPerBlock + threadIdx.x / 64u;
+         c < n_cells; c += stride) {
+        const uint32_t b = off[c], n = off[c + 1] - b;
+        uint32_t cnt = 0;
+        for (uint32_t base = 0; base < n; base += 64u) {
+            const bool live = base + lane < n && xi[b + base + lane] != 0;
+            cnt += static_cast<uint32_t>(__popcll(__ballot(live)));
+        }
+        if (lane == 0) out[c] = cnt;
+    }
+}
+
+// Largest P_ij per cell over the pairs (order[2m], order[2m+1]), m < n_live/2,
+// of a pairing written by the permutation launch; the maximum over all cells
+// goes to *gmax as the bit pattern of a non-negative double.
+__global__ __launch_bounds__(kDiagBlock) void k_probe_pairs(
+    const uint32_t* __restrict__ off, const double* __restrict__ dV,
+    const uint64_t* __restrict__ xi, const double* __restrict__ r,
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ nlive, uint32_t n_cells,
+    uint32_t kernel, KernelParams kp, double dt, double* __restrict__ cell_max,
+    unsigned long long* __restrict__ gmax)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kDiagCellsPerBlock;
+    double wave_best = 0.0;
+    for (uint64_t c = static_cast<uint64_t>(blockIdx.x) * kDiagCellsPerBlock + threadIdx.x / 64u;
+         c < n_cells; c += stride) {
+        const uint32_t b = off[c], n = nlive[c];
+        double best = 0.0;
+        if (n >= 2) {
+            const double scale = upscale_factor(n);
+            const double dVc = dV[c];
+            for (uint32_t m = lane; m < n / 2u; m += 64u) {
+                const uint32_t ia = b + order[b + 2u * m], ib = b + order[b + 2u * m + 1u];
+                const uint64_t xa = xi[ia], xb = xi[ib];
+                const double K = collection_kernel(kernel, kp, r[ia], r[ib]);
+                const double p = collision_probability(xa >= xb ? xa : xb, K, dt, dVc, scale);
+                best = fmax(best, p);
+            }
+        }
+        best = wave_max(best);
+        if (lane == 0 && cell_max) cell_max[c] = best;
+        wave_best = fmax(wave_best, best);
+    }
+    if (lane == 0 && wave_best > 0.0)
+        atomicMax(gmax, static_cast<unsigned long long>(__double_as_longlong(wave_best)));
+}
+
+}  // namespace
+}  // namespace sdm

@@ -74,6 +74,12 @@ def lib() -> ctypes.CDLL:
         "sdm_get_layout": (ctypes.c_int, [_P, _P, _P]),
         "sdm_debug_permutation": (ctypes.c_int, [_P, _u64, _u64, _P, _P]),
         "sdm_get_plan": (ctypes.c_int, [_P, _P, _P, _P]),
+        "sdm_diag_sd_conc": (ctypes.c_int, [_P, _P]),
+        "sdm_diag_moments": (ctypes.c_int, [_P, _u32, _dbl, _dbl, _P, _P]),
+        "sdm_probe_probability": (ctypes.c_int, [_P, _dbl, ctypes.c_int, _u64, _u64, _P, _P]),
+        "sdm_coalesce_substeps": (ctypes.c_int, [_P, _dbl, _u32, ctypes.c_int, _u64, _u64]),
+        "sdm_coalesce_adaptive": (ctypes.c_int, [_P, _dbl, _dbl, _u32, ctypes.c_int, _u64, _u64,
+                                                 _P]),
         "sdm_get_launch_config": (ctypes.c_int, [_P, _P]),
         "sdm_set_launch_config": (ctypes.c_int, [_P, _P]),
         "sdm_autotune_workspace_bytes": (_sz, [_P]),
@@ -175,6 +181,54 @@ class Context:
         k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
         _check(lib().sdm_coalesce_step(self._ctx, float(dt), k, int(seed), int(step)),
                "sdm_coalesce_step")
+
+    def substeps(self, dt: float, n_substeps: int, kernel: int | str, seed: int, first_step: int):
+        """n_substeps steps of dt / n_substeps with counters first_step, first_step + 1, ..."""
+        k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        _check(lib().sdm_coalesce_substeps(self._ctx, float(dt), int(n_substeps), k, int(seed),
+                                           int(first_step)), "sdm_coalesce_substeps")
+
+    def adaptive(self, dt: float, p_limit: float, max_substeps: int, kernel: int | str, seed: int,
+                 first_step: int) -> int:
+        """Probe, then ceil(pmax / p_limit) sub-steps; returns the number taken."""
+        k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        n = _u32()
+        _check(lib().sdm_coalesce_adaptive(self._ctx, float(dt), float(p_limit), int(max_substeps),
+                                           k, int(seed), int(first_step), ctypes.byref(n)),
+               "sdm_coalesce_adaptive")
+        return int(n.value)
+
+    def probe(self, dt: float, kernel: int | str, seed: int, step: int, per_cell: bool = False):
+        """Largest P_ij of step ``step`` (and, with ``per_cell``, a float64 tensor of the
+        per-cell maxima); the state is not changed."""
+        k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        cm = torch.empty(max(1, self.n_cells), dtype=torch.float64, device=self.device) \
+            if per_cell else None
+        g = _dbl()
+        torch.cuda.synchronize(self.device)
+        _check(lib().sdm_probe_probability(self._ctx, float(dt), k, int(seed), int(step),
+                                           _dptr(cm), ctypes.byref(g)), "sdm_probe_probability")
+        return (float(g.value), cm[: self.n_cells]) if per_cell else float(g.value)
+
+    def sd_conc(self):
+        """Live super-droplets per cell (int32 tensor holding uint32 values)."""
+        out = torch.empty(max(1, self.n_cells), dtype=torch.int32, device=self.device)
+        torch.cuda.synchronize(self.device)
+        _check(lib().sdm_diag_sd_conc(self._ctx, _dptr(out)), "sdm_diag_sd_conc")
+        torch.cuda.synchronize(self.device)
+        return out[: self.n_cells]
+
+    def moments(self, k: int, r_min: float = 0.0, r_max: float = float("inf"), rho_d=None):
+        """Per-cell k-th radius moment, (rho_d dV)^-1 sum xi r^k over r in [r_min, r_max]."""
+        out = torch.empty(max(1, self.n_cells), dtype=torch.float64, device=self.device)
+        rho = None
+        if rho_d is not None:
+            rho = torch.as_tensor(rho_d, dtype=torch.float64).to(self.device).contiguous()
+        torch.cuda.synchronize(self.device)
+        _check(lib().sdm_diag_moments(self._ctx, int(k), float(r_min), float(r_max), _dptr(rho),
+                                      _dptr(out)), "sdm_diag_moments")
+        torch.cuda.synchronize(self.device)
+        return out[: self.n_cells]
 
     def state(self):
         """(xi int64-bits-of-uint64 tensor, r float64 tensor) in input order."""
