@@ -27,6 +27,12 @@ _LIB_PATH = os.path.join(_BUILD_DIR, "libsdm_oracle.so")
 GOLOVIN = 0
 GEOMETRIC = 1
 
+# Outcome rules (bit flags): the paper's release rule (one event when u < P_ij,
+# equal multiplicities leave a zero-multiplicity particle) and recycling of
+# zero-multiplicity particles at the start of each step.
+RULE_FIDELITY = 1
+RULE_RECYCLE = 2
+
 # Default kernel parameters: Golovin b = 1500 s^-1; terminal velocity after
 # Rogers & Yau (1989) in SI units (k1 r^2 below 40 um, k2 r up to 600 um,
 # k3 sqrt(r) above); collection efficiency E = 1.
@@ -81,6 +87,14 @@ def lib() -> ctypes.CDLL:
     L.oracle_cell_order.restype = u32
     L.oracle_step.argtypes = [u32, P, P, P, P, dbl, i32, P, u64, u32, u32, P]
     L.oracle_step.restype = i32
+    L.oracle_step_rules.argtypes = [u32, P, P, P, P, dbl, i32, P, u64, u32, u32, P, u32]
+    L.oracle_step_rules.restype = i32
+    L.oracle_gamma_fidelity.argtypes = [dbl, dbl]
+    L.oracle_gamma_fidelity.restype = u64
+    L.oracle_collide_pair_fidelity.argtypes = [u64, P, P, P, P]
+    L.oracle_collide_pair_fidelity.restype = None
+    L.oracle_recycle_cell.argtypes = [u32, P, P]
+    L.oracle_recycle_cell.restype = u32
     L.oracle_sort_by_cell.argtypes = [u64, P, u32, P, P]
     L.oracle_sort_by_cell.restype = i32
     L.oracle_moments.argtypes = [u32, P, P, P, P, i32, dbl, dbl, P, P]
@@ -157,6 +171,26 @@ def collide_pair(g: int, xi_j: int, r_j: float, xi_k: int, r_k: float):
     return int(a[0]), float(r[0]), int(a[1]), float(r[1])
 
 
+def gamma_fidelity(p: float, u: float) -> int:
+    return int(lib().oracle_gamma_fidelity(p, u))
+
+
+def collide_pair_fidelity(g: int, xi_j: int, r_j: float, xi_k: int, r_k: float):
+    a = np.array([xi_j, xi_k], dtype=np.uint64)
+    r = np.array([r_j, r_k], dtype=np.float64)
+    lib().oracle_collide_pair_fidelity(g, a.ctypes.data, r.ctypes.data, a.ctypes.data + 8,
+                                       r.ctypes.data + 8)
+    return int(a[0]), float(r[0]), int(a[1]), float(r[1])
+
+
+def recycle_cell(xi_cell, r_cell):
+    """Recycle one cell in place on copies; returns (xi, r, number recycled)."""
+    xi = np.array(xi_cell, dtype=np.uint64)
+    r = np.array(r_cell, dtype=np.float64)
+    n = lib().oracle_recycle_cell(xi.size, _ptr(xi), _ptr(r))
+    return xi, r, int(n)
+
+
 def cell_order(xi_cell: np.ndarray, seed: int, cell: int, step: int) -> np.ndarray:
     xi_cell = np.ascontiguousarray(xi_cell, dtype=np.uint64)
     order = np.zeros(max(1, xi_cell.size), dtype=np.uint32)
@@ -184,7 +218,7 @@ class SlotState:
         self.stats = np.zeros(2, dtype=np.uint64)
 
     def step(self, dt: float, kind: int, seed: int, step: int, params=None,
-             cells: tuple | None = None, cell_index_base: int = 0):
+             cells: tuple | None = None, cell_index_base: int = 0, rules: int = 0):
         """One coalescence step over all cells, or over the cell range ``cells``."""
         p = _params(params)
         c0, c1 = (0, self.n_cells) if cells is None else cells
@@ -196,28 +230,28 @@ class SlotState:
         xi_view = self.xi[base:]
         r_view = self.r[base:]
         st = np.zeros(2, dtype=np.uint64)
-        lib().oracle_step(c1 - c0, _ptr(rel), _ptr(dv), xi_view.ctypes.data,
-                          r_view.ctypes.data, dt, kind, _ptr(p), seed, step,
-                          cell_index_base + c0, _ptr(st))
+        lib().oracle_step_rules(c1 - c0, _ptr(rel), _ptr(dv), xi_view.ctypes.data,
+                                r_view.ctypes.data, dt, kind, _ptr(p), seed, step,
+                                cell_index_base + c0, _ptr(st), rules)
         self.stats += st
         return st
 
-    def step_parallel(self, dt, kind, seed, step, params=None, threads: int = 8):
+    def step_parallel(self, dt, kind, seed, step, params=None, threads: int = 8, rules: int = 0):
         """Same result as ``step``: cells are independent, so ranges of cells run
         in separate threads (ctypes releases the GIL)."""
         n = self.n_cells
         if threads <= 1 or n < 2 * threads:
-            return self.step(dt, kind, seed, step, params)
+            return self.step(dt, kind, seed, step, params, rules=rules)
         bounds = np.linspace(0, n, threads + 1).astype(int)
         parts = [(int(bounds[i]), int(bounds[i + 1])) for i in range(threads)]
         with ThreadPoolExecutor(threads) as ex:
-            res = list(ex.map(lambda cr: self._step_range(dt, kind, seed, step, params, cr),
+            res = list(ex.map(lambda cr: self._step_range(dt, kind, seed, step, params, cr, rules),
                               parts))
         st = np.sum(res, axis=0).astype(np.uint64)
         self.stats += st
         return st
 
-    def _step_range(self, dt, kind, seed, step, params, cr):
+    def _step_range(self, dt, kind, seed, step, params, cr, rules=0):
         p = _params(params)
         c0, c1 = cr
         off = np.ascontiguousarray(self.offsets[c0:c1 + 1])
@@ -225,9 +259,9 @@ class SlotState:
         base = int(off[0])
         rel = np.ascontiguousarray(off - np.uint64(base))
         st = np.zeros(2, dtype=np.uint64)
-        lib().oracle_step(c1 - c0, _ptr(rel), _ptr(dv), self.xi[base:].ctypes.data,
-                          self.r[base:].ctypes.data, dt, kind, _ptr(p), seed, step, c0,
-                          _ptr(st))
+        lib().oracle_step_rules(c1 - c0, _ptr(rel), _ptr(dv), self.xi[base:].ctypes.data,
+                                self.r[base:].ctypes.data, dt, kind, _ptr(p), seed, step, c0,
+                                _ptr(st), rules)
         return st
 
     def moments(self, k: int, r_min: float = 0.0, r_max: float = float("inf"), rho_d=None):

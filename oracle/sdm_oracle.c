@@ -30,6 +30,11 @@
  *     (instead of leaving a zero-multiplicity particle for recycling);
  *   - random numbers from counter-based Philox4x32-10 instead of the
  *     Mersenne Twister the paper's release uses (Sect. 5.3);
+ *   - the release rules (ORACLE_RULE_FIDELITY) keep the same pairing, P_ij
+ *     and mass-conserving outcome, with one event when u < P_ij and a zero
+ *     multiplicity left on the first pair member when multiplicities are
+ *     equal; recycling (ORACLE_RULE_RECYCLE) runs within each cell at the
+ *     start of every step, before the pairing, as in oracle_recycle_cell;
  *   - moments count live super-droplets only, the radius range is closed at
  *     both ends, and rho_d defaults to 1 (moments per unit volume) when no
  *     dry-air density is given; the summation order is fixed (see
@@ -341,6 +346,93 @@ void oracle_collide_pair(uint64_t g, uint64_t *xi_j, double *r_j, uint64_t *xi_k
     }
 }
 
+/* The outcome rules of the paper's own release (Sect. 5.1.4), selected by
+ * ORACLE_RULE_FIDELITY: a collision is triggered when the uniform deviate is
+ * below P_ij, and then exactly one event happens (no multiple coalescence);
+ * equal multiplicities collide by the same scheme, which leaves the larger
+ * (first) super-droplet with multiplicity zero. */
+#define ORACLE_RULE_FIDELITY 1u
+/* Recycling of zero-multiplicity super-droplets at the start of every step. */
+#define ORACLE_RULE_RECYCLE 2u
+
+uint64_t oracle_gamma_fidelity(double p, double u)
+{
+    return u < p ? 1u : 0u;
+}
+
+void oracle_collide_pair_fidelity(uint64_t g, uint64_t *xi_j, double *r_j, uint64_t *xi_k,
+                                  double *r_k)
+{
+    (void)r_j;
+    if (g == 0) return;
+    double rj3 = (*r_j * *r_j) * *r_j;
+    double rk3 = (*r_k * *r_k) * *r_k;
+    double vol = rj3 + rk3;
+    *r_k = oracle_cbrt_rn(vol);
+    *xi_j = *xi_j - *xi_k;   /* zero when the multiplicities are equal */
+}
+
+/* Recycling in one cell (the zero-multiplicity rule of Sect. 5.1.4, applied
+ * within the cell).  Let z be the number of dead slots (xi = 0) and L the
+ * number of live ones.  The donors are the min(z, L) live slots ranked first
+ * by multiplicity, largest first, ties broken by the lower slot; those with
+ * xi >= 2 can be split.  Taken in ascending slot order, the k-th splittable
+ * donor d hands its radius and floor(xi_d / 2) of its multiplicity to the
+ * k-th dead slot (ascending slot order) and keeps the rest.  Returns the
+ * number of recycled slots. */
+typedef struct { uint64_t xi; uint32_t slot; } ranked_slot;
+
+static int cmp_ranked_slot(const void *pa, const void *pb)
+{
+    const ranked_slot *a = (const ranked_slot *)pa, *b = (const ranked_slot *)pb;
+    if (a->xi != b->xi) return a->xi > b->xi ? -1 : 1;   /* larger multiplicity first */
+    if (a->slot != b->slot) return a->slot < b->slot ? -1 : 1;
+    return 0;
+}
+
+static int cmp_u32(const void *pa, const void *pb)
+{
+    uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+uint32_t oracle_recycle_cell(uint32_t n_slots, uint64_t *xi, double *r)
+{
+    uint32_t n = n_slots ? n_slots : 1u;
+    uint32_t *dead = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    uint32_t *donor = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    ranked_slot *live = (ranked_slot *)malloc(sizeof(ranked_slot) * n);
+    uint32_t z = 0, L = 0;
+    for (uint32_t s = 0; s < n_slots; ++s) {
+        if (xi[s] == 0) {
+            dead[z++] = s;
+        } else {
+            live[L].xi = xi[s];
+            live[L].slot = s;
+            ++L;
+        }
+    }
+    uint32_t nd = 0;
+    if (z > 0 && L > 0) {
+        qsort(live, L, sizeof(ranked_slot), cmp_ranked_slot);
+        uint32_t take = z < L ? z : L;
+        for (uint32_t i = 0; i < take; ++i)
+            if (live[i].xi >= 2u) donor[nd++] = live[i].slot;
+        qsort(donor, nd, sizeof(uint32_t), cmp_u32);
+        for (uint32_t i = 0; i < nd; ++i) {
+            uint32_t d = donor[i], t = dead[i];
+            uint64_t half = xi[d] / 2u;
+            xi[t] = half;
+            r[t] = r[d];
+            xi[d] = xi[d] - half;
+        }
+    }
+    free(dead);
+    free(donor);
+    free(live);
+    return nd;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Random grouping into non-overlapping pairs                                */
 /* ------------------------------------------------------------------------ */
@@ -380,9 +472,10 @@ uint32_t oracle_cell_order(uint32_t n_slots, const uint64_t *xi, uint64_t seed,
 /* One step over cells [0, n_cells) stored slot-contiguously: cell c owns
  * slots [offsets[c], offsets[c+1]).  The RNG cell index of cell c is
  * cell_index_base + c.  stats[0] += pair tests, stats[1] += collisions. */
-int oracle_step(uint32_t n_cells, const uint64_t *offsets, const double *dV,
-                uint64_t *xi, double *r, double dt, int kernel, const double *params,
-                uint64_t seed, uint32_t step, uint32_t cell_index_base, uint64_t *stats)
+int oracle_step_rules(uint32_t n_cells, const uint64_t *offsets, const double *dV,
+                      uint64_t *xi, double *r, double dt, int kernel, const double *params,
+                      uint64_t seed, uint32_t step, uint32_t cell_index_base, uint64_t *stats,
+                      uint32_t rules)
 {
     uint32_t max_slots = 0;
     for (uint32_t c = 0; c < n_cells; ++c) {
@@ -394,6 +487,7 @@ int oracle_step(uint32_t n_cells, const uint64_t *offsets, const double *dV,
         uint64_t base = offsets[c];
         uint32_t n_slots = (uint32_t)(offsets[c + 1] - base);
         uint32_t cell = cell_index_base + c;
+        if (rules & ORACLE_RULE_RECYCLE) oracle_recycle_cell(n_slots, xi + base, r + base);
         uint32_t n = oracle_cell_order(n_slots, xi + base, seed, cell, step, order);
         if (n < 2) continue;
         double scale = oracle_upscale(n);
@@ -405,14 +499,28 @@ int oracle_step(uint32_t n_cells, const uint64_t *offsets, const double *dV,
             double K = oracle_kernel(kernel, params, r[a], r[b]);
             double p = oracle_probability(xi[j], K, dt, dV[c], scale);
             double u = oracle_pair_uniform(seed, cell, step, m);
-            uint64_t g = oracle_gamma(p, u, xi[j], xi[k]);
-            if (g > 0) stats[1] += 1;
-            oracle_collide_pair(g, &xi[j], &r[j], &xi[k], &r[k]);
+            if (rules & ORACLE_RULE_FIDELITY) {
+                uint64_t g = oracle_gamma_fidelity(p, u);
+                if (g > 0) stats[1] += 1;
+                oracle_collide_pair_fidelity(g, &xi[j], &r[j], &xi[k], &r[k]);
+            } else {
+                uint64_t g = oracle_gamma(p, u, xi[j], xi[k]);
+                if (g > 0) stats[1] += 1;
+                oracle_collide_pair(g, &xi[j], &r[j], &xi[k], &r[k]);
+            }
         }
         stats[0] += n / 2u;
     }
     free(order);
     return 0;
+}
+
+int oracle_step(uint32_t n_cells, const uint64_t *offsets, const double *dV,
+                uint64_t *xi, double *r, double dt, int kernel, const double *params,
+                uint64_t seed, uint32_t step, uint32_t cell_index_base, uint64_t *stats)
+{
+    return oracle_step_rules(n_cells, offsets, dV, xi, r, dt, kernel, params, seed, step,
+                             cell_index_base, stats, 0u);
 }
 
 /* Stable sort of super-droplets by cell (ties in input order).  Writes the
