@@ -149,6 +149,38 @@ sdm_status sdm_debug_permutation(sdm_ctx *ctx, uint64_t seed, uint64_t step,
                                  uint32_t *order_out, uint32_t *n_live_out);
 
 /* ------------------------------------------------------------------------ */
+/* Outcome rules (Sect. 5.1.4).  By default a step applies multiple          */
+/* coalescence: gamma = floor(P_ij) + [u < frac(P_ij)] events, capped at     */
+/* floor(xi_j / xi_k), and equal multiplicities afterwards split xi_k        */
+/* between both particles.  The flags select the paper's own release rules.  */
+/* ------------------------------------------------------------------------ */
+typedef enum {
+    /* one event when u < P_ij, never more; equal multiplicities leave the
+     * larger (first in pair order) particle with multiplicity 0 and its radius */
+    SDM_RULE_RELEASE = 1,
+    /* recycle zero-multiplicity particles at the start of every step (see
+     * sdm_recycle) */
+    SDM_RULE_RECYCLE = 2
+} sdm_rule;
+
+/* Set / read the rule flags every later step of the context applies (steps,
+ * sub-steps, adaptive sub-steps).  Errors: SDM_EINVAL (unknown flag). */
+sdm_status sdm_set_rules(sdm_ctx *ctx, uint32_t rules);
+sdm_status sdm_get_rules(sdm_ctx *ctx, uint32_t *rules);
+
+/* Recycle now, within each cell (the zero-multiplicity rule of Sect. 5.1.4):
+ * with z dead (xi = 0) and L live slots, the min(z, L) live slots ranked first
+ * by multiplicity (largest first, ties to the lower slot) are the donors; in
+ * ascending slot order the k-th donor with xi >= 2 gives its radius and
+ * floor(xi / 2) of its multiplicity to the k-th dead slot (ascending slot
+ * order) and keeps the rest.  Enqueued on the context stream; uses the
+ * context's probe scratch. */
+sdm_status sdm_recycle(sdm_ctx *ctx);
+
+/* Total number of recycled slots since sdm_init (host out).  Synchronises. */
+sdm_status sdm_get_recycled(sdm_ctx *ctx, uint64_t *total);
+
+/* ------------------------------------------------------------------------ */
 /* Gridded diagnostics (Sect. 5.2, the particle-based scheme's diagnostics:  */
 /* super-droplet concentration and k-th radius moment per cell).  Both are   */
 /* enqueued on the context stream and do not synchronise it.                 */
@@ -197,7 +229,9 @@ sdm_status sdm_coalesce_substeps(sdm_ctx *ctx, double dt, uint32_t n_substeps, s
  * n = ceil(pmax / p_limit) sub-steps (1 if pmax <= p_limit, at most
  * max_substeps) and run sdm_coalesce_substeps(ctx, dt, n, kernel, seed,
  * first_step).  The first sub-step uses the probed pairing, so its largest
- * P_ij is pmax / n up to rounding; later sub-steps draw new pairings.
+ * P_ij is pmax / n up to rounding; later sub-steps draw new pairings.  With
+ * SDM_RULE_RECYCLE the recycling runs before the probe, and the first
+ * sub-step does not recycle again.
  * *substeps_out (host, nullable) = n; the caller advances its step counter by
  * n.  Synchronises the stream once (to read pmax).
  * Errors: SDM_EINVAL (p_limit not finite and > 0, max_substeps == 0, or as

@@ -2,6 +2,7 @@
 // state, counter, layout, plan and permutation queries of a context.
 #include "runtime.hpp"
 #include "diag_kernels.hpp"
+#include "recycle_kernels.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -37,6 +38,7 @@ struct sdm_ctx {
     std::vector<uint32_t> sizes;   // storage slots per cell (host copy)
     uint32_t n_groups = 0, n_wave_cells = 0, n_block = 0;
     LaunchShape shape;
+    uint32_t rules = 0;   // sdm_rule flags applied by every step
 };
 
 namespace {
@@ -108,6 +110,7 @@ StepArgs base_args(const sdm_ctx* x)
     a.off_end = x->offsets + 1;
     a.dV = x->dV;
     a.kp = to_kp(x->params);
+    a.rules = x->rules;
     a.stats = x->stats;
     a.scr_kv = x->scr_kv;
     a.scr_tmp = x->scr_tmp;
@@ -274,6 +277,16 @@ static sdm_status step_args(sdm_ctx* x, double dt, sdm_kernel kernel, uint64_t s
     return SDM_OK;
 }
 
+static sdm_status enqueue_recycle(sdm_ctx* x)
+{
+    if (x->n_cells == 0) return SDM_OK;
+    hipLaunchKernelGGL(k_recycle, dim3(grid_for(x->n_cells, kRecycleCellsPerBlock, 1u << 16)),
+                       dim3(kRecycleBlock), 0, x->stream, x->offsets, x->xi, x->r, x->n_cells,
+                       x->probe_order, x->stats + kRecycledStat);
+    SDM_LAUNCHED();
+    return SDM_OK;
+}
+
 static sdm_status launch(sdm_ctx* x, const StepArgs& a, bool perm)
 {
     return launch_step(x->stream, a, x->group_begin, x->group_end, x->n_groups, x->block_items,
@@ -286,6 +299,7 @@ extern "C" sdm_status sdm_coalesce_step(sdm_ctx* x, double dt, sdm_kernel kernel
     SDM_TRY(check_ctx(x));
     StepArgs a;
     SDM_TRY(step_args(x, dt, kernel, seed, step, &a));
+    if (x->rules & kRuleRecycle) SDM_TRY(enqueue_recycle(x));
     return launch(x, a, false);
 }
 
@@ -404,25 +418,35 @@ extern "C" sdm_status sdm_probe_probability(sdm_ctx* x, double dt, sdm_kernel ke
     return SDM_OK;
 }
 
-extern "C" sdm_status sdm_coalesce_substeps(sdm_ctx* x, double dt, uint32_t n_substeps,
-                                            sdm_kernel kernel, uint64_t seed, uint64_t first_step)
+// n sub-steps of dt / n; the first one recycles only if recycle_first is set
+// (the adaptive path has recycled already, before probing).
+static sdm_status run_substeps(sdm_ctx* x, double dt, uint32_t n_substeps, sdm_kernel kernel,
+                               uint64_t seed, uint64_t first_step, bool recycle_first)
 {
-    SDM_TRY(check_ctx(x));
     if (n_substeps == 0) {
         set_error("n_substeps must be >= 1");
         return SDM_EINVAL;
     }
-    if (first_step + n_substeps > (1ull << 32) || first_step >= (1ull << 32)) {
+    if (first_step >= (1ull << 32) || first_step + n_substeps > (1ull << 32)) {
         set_error("step counters must stay below 2^32");
         return SDM_EINVAL;
     }
     const double h = dt / static_cast<double>(n_substeps);
+    StepArgs a;
+    SDM_TRY(step_args(x, h, kernel, seed, first_step, &a));   // validates before any launch
     for (uint32_t i = 0; i < n_substeps; ++i) {
-        StepArgs a;
         SDM_TRY(step_args(x, h, kernel, seed, first_step + i, &a));
+        if ((x->rules & kRuleRecycle) && (i > 0 || recycle_first)) SDM_TRY(enqueue_recycle(x));
         SDM_TRY(launch(x, a, false));
     }
     return SDM_OK;
+}
+
+extern "C" sdm_status sdm_coalesce_substeps(sdm_ctx* x, double dt, uint32_t n_substeps,
+                                            sdm_kernel kernel, uint64_t seed, uint64_t first_step)
+{
+    SDM_TRY(check_ctx(x));
+    return run_substeps(x, dt, n_substeps, kernel, seed, first_step, true);
 }
 
 extern "C" sdm_status sdm_coalesce_adaptive(sdm_ctx* x, double dt, double p_limit,
@@ -435,12 +459,63 @@ extern "C" sdm_status sdm_coalesce_adaptive(sdm_ctx* x, double dt, double p_limi
         set_error("p_limit must be finite and > 0 and max_substeps >= 1");
         return SDM_EINVAL;
     }
+    if (first_step >= (1ull << 32) || first_step + max_substeps > (1ull << 32)) {
+        set_error("step counters must stay below 2^32");
+        return SDM_EINVAL;
+    }
+    StepArgs a;
+    SDM_TRY(step_args(x, dt, kernel, seed, first_step, &a));   // validates before any launch
+    // recycle first, so that the probed pairing is the one the first sub-step uses
+    if (x->rules & kRuleRecycle) SDM_TRY(enqueue_recycle(x));
     double pmax = 0.0;
     SDM_TRY(enqueue_probe(x, dt, kernel, seed, first_step, nullptr));
     SDM_TRY(read_probe_max(x, &pmax));
     const uint32_t n = substep_count(pmax, p_limit, max_substeps);
-    SDM_TRY(sdm_coalesce_substeps(x, dt, n, kernel, seed, first_step));
+    SDM_TRY(run_substeps(x, dt, n, kernel, seed, first_step, false));
     if (substeps_out) *substeps_out = n;
+    return SDM_OK;
+}
+
+extern "C" sdm_status sdm_set_rules(sdm_ctx* x, uint32_t rules)
+{
+    SDM_TRY(check_ctx(x));
+    if (rules & ~static_cast<uint32_t>(SDM_RULE_RELEASE | SDM_RULE_RECYCLE)) {
+        set_error("unknown rule flags 0x%x", rules);
+        return SDM_EINVAL;
+    }
+    x->rules = rules;
+    return SDM_OK;
+}
+
+extern "C" sdm_status sdm_get_rules(sdm_ctx* x, uint32_t* rules)
+{
+    SDM_TRY(check_ctx(x));
+    if (!rules) {
+        set_error("rules is NULL");
+        return SDM_EINVAL;
+    }
+    *rules = x->rules;
+    return SDM_OK;
+}
+
+extern "C" sdm_status sdm_recycle(sdm_ctx* x)
+{
+    SDM_TRY(check_ctx(x));
+    return enqueue_recycle(x);
+}
+
+extern "C" sdm_status sdm_get_recycled(sdm_ctx* x, uint64_t* total)
+{
+    SDM_TRY(check_ctx(x));
+    if (!total) {
+        set_error("total is NULL");
+        return SDM_EINVAL;
+    }
+    unsigned long long v = 0;
+    SDM_HIP(hipMemcpyAsync(&v, x->stats + kRecycledStat, sizeof(v), hipMemcpyDeviceToHost,
+                           x->stream));
+    SDM_HIP(hipStreamSynchronize(x->stream));
+    *total = v;
     return SDM_OK;
 }
 

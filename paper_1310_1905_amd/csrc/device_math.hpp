@@ -229,6 +229,12 @@ __device__ __forceinline__ uint64_t collision_count(double p, double u, uint64_t
     return g < cap ? g : cap;
 }
 
+// The release rule of Sect. 5.1.4: one event when u < p, never more.
+__device__ __forceinline__ uint64_t collision_count_release(double p, double u)
+{
+    return (u < p) ? 1u : 0u;
+}
+
 // Outcome of g > 0 events between j (xi_j >= xi_k) and k.
 struct PairState {
     uint64_t xj, xk;
@@ -236,7 +242,9 @@ struct PairState {
     bool j_changed_r;   // equal-split case: both radii (and both xi) change
 };
 
-__device__ __forceinline__ void apply_collisions(uint64_t g, PairState& s)
+// release = true: equal multiplicities leave j with zero multiplicity (and its
+// radius) instead of splitting xi_k between both.
+__device__ __forceinline__ void apply_collisions(uint64_t g, PairState& s, bool release = false)
 {
     const double rj3 = (s.rj * s.rj) * s.rj;
     const double rk3 = (s.rk * s.rk) * s.rk;
@@ -249,12 +257,13 @@ __device__ __forceinline__ void apply_collisions(uint64_t g, PairState& s)
         s.rk = rn;
         s.j_changed_r = false;
     } else {
-        const uint64_t half = s.xk >> 1;
+        // equal split, or under the release rule j left empty (half = 0)
+        const uint64_t half = release ? 0u : (s.xk >> 1);
         s.xj = half;
         s.xk = s.xk - half;
         s.rj = rn;
         s.rk = rn;
-        s.j_changed_r = true;
+        s.j_changed_r = !release;
     }
 }
 

@@ -30,6 +30,12 @@ constexpr int kWave = 64;
 constexpr int kStatSlots = 64;                     // spread of the global counters
 constexpr int kStatStride = 16;                    // 128 bytes between counter pairs
 
+// Outcome rules of a step (bit flags, as the public rule flags).
+enum : uint32_t { kRuleRelease = 1u, kRuleRecycle = 2u };
+// Index of the recycled-slot counter in the single-run counter array (a free
+// word of the first counter slot).
+constexpr int kRecycledStat = 2;
+
 // Per-instance record of a batch (device table).
 struct InstanceRec {
     uint64_t seed;
@@ -66,6 +72,7 @@ struct StepArgs {
     uint32_t kernel;
     double dt;
     KernelParams kp;
+    uint32_t rules;               // kRuleRelease: one event when u < P_ij, zero on equal xi
     unsigned long long* stats;    // single run: kStatSlots x {pair tests, collisions}
     // workgroup-tier scratch, indexed by storage slot
     uint64_t* scr_kv;
@@ -210,9 +217,10 @@ __device__ __forceinline__ bool collide_pair_global(const StepArgs& a, const Cel
     s.rj = a_is_j ? ra : rb;
     s.rk = a_is_j ? rb : ra;
     const double p = collision_probability(s.xj, K, j.dt, j.dV, scale);
-    const uint64_t g = collision_count(p, u, s.xj, s.xk);
+    const bool release = (a.rules & kRuleRelease) != 0;
+    const uint64_t g = release ? collision_count_release(p, u) : collision_count(p, u, s.xj, s.xk);
     if (g == 0) return false;
-    apply_collisions(g, s);
+    apply_collisions(g, s, release);
     const uint32_t slot_j = a_is_j ? sa : sb;
     const uint32_t slot_k = a_is_j ? sb : sa;
     const uint64_t gj = static_cast<uint64_t>(j.off) + slot_j;
@@ -321,7 +329,7 @@ __device__ __forceinline__ void flush_collisions(const StepArgs& a, const CollEn
             s.xk = a.xi[e.gk];
             s.rj = a.r[e.gj];
             s.rk = a.r[e.gk];
-            apply_collisions(e.g, s);
+            apply_collisions(e.g, s, (a.rules & kRuleRelease) != 0);
             a.xi[e.gj] = s.xj;
             a.r[e.gk] = s.rk;
             if (s.j_changed_r) {
@@ -632,7 +640,8 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
                 const uint64_t xj = a_is_j ? xa : xb;
                 const uint64_t xk = a_is_j ? xb : xa;
                 const double prob = collision_probability(xj, Kab, job.dt, L.dV[c], L.scale[c]);
-                gam = collision_count(prob, u, xj, xk);
+                // the release rule is the capped count of min(P_ij, 1)
+                gam = collision_count((a.rules & kRuleRelease) ? fmin(prob, 1.0) : prob, u, xj, xk);
                 gj = g_first + (a_is_j ? sa : sb);
                 gk = g_first + (a_is_j ? sb : sa);
             }

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libsdm.so")
 GOLOVIN = 0
 GEOMETRIC = 1
 KERNELS = {"golovin": GOLOVIN, "geometric": GEOMETRIC}
+RULE_RELEASE = 1   # one event when u < P_ij; equal multiplicities leave a zero
+RULE_RECYCLE = 2   # recycle zero-multiplicity particles at the start of each step
 
 _P = ctypes.c_void_p
 _u32, _u64, _i32, _dbl, _sz = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
@@ -74,6 +76,10 @@ def lib() -> ctypes.CDLL:
         "sdm_get_layout": (ctypes.c_int, [_P, _P, _P]),
         "sdm_debug_permutation": (ctypes.c_int, [_P, _u64, _u64, _P, _P]),
         "sdm_get_plan": (ctypes.c_int, [_P, _P, _P, _P]),
+        "sdm_set_rules": (ctypes.c_int, [_P, _u32]),
+        "sdm_get_rules": (ctypes.c_int, [_P, _P]),
+        "sdm_recycle": (ctypes.c_int, [_P]),
+        "sdm_get_recycled": (ctypes.c_int, [_P, _P]),
         "sdm_diag_sd_conc": (ctypes.c_int, [_P, _P]),
         "sdm_diag_moments": (ctypes.c_int, [_P, _u32, _dbl, _dbl, _P, _P]),
         "sdm_probe_probability": (ctypes.c_int, [_P, _dbl, ctypes.c_int, _u64, _u64, _P, _P]),
@@ -181,6 +187,23 @@ class Context:
         k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
         _check(lib().sdm_coalesce_step(self._ctx, float(dt), k, int(seed), int(step)),
                "sdm_coalesce_step")
+
+    def set_rules(self, rules: int):
+        """SDM rule flags (RULE_RELEASE | RULE_RECYCLE) for every later step."""
+        _check(lib().sdm_set_rules(self._ctx, int(rules)), "sdm_set_rules")
+
+    def rules(self) -> int:
+        v = _u32()
+        _check(lib().sdm_get_rules(self._ctx, ctypes.byref(v)), "sdm_get_rules")
+        return int(v.value)
+
+    def recycle(self):
+        _check(lib().sdm_recycle(self._ctx), "sdm_recycle")
+
+    def recycled(self) -> int:
+        v = _u64()
+        _check(lib().sdm_get_recycled(self._ctx, ctypes.byref(v)), "sdm_get_recycled")
+        return int(v.value)
 
     def substeps(self, dt: float, n_substeps: int, kernel: int | str, seed: int, first_step: int):
         """n_substeps steps of dt / n_substeps with counters first_step, first_step + 1, ..."""
