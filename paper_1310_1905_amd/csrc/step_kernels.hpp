@@ -265,7 +265,7 @@ struct alignas(16) GroupLds {
         // ucall entry are write-only dummies that dead slots are sent to
         struct {
             uint64_t kv[CAP + 2];           // (key << 32 | slot) grouped by bucket
-            uint32_t start[2 * CAP + 4];    // bucket counts, then bucket starts
+            uint32_t start[CAP + 4];        // bucket counts, then bucket starts
             uint32_t keys[CAP];             // shuffle key of every group slot
             uint32_t slotinfo[CAP];         // cell | bucket base << 8 | lg << 24 (base < 2048)
             uint32_t call[CAP / 4 + kGroupMaxCells];   // key call: slot base | cell << 9 | q << 15 | (words-1) << 22
@@ -439,8 +439,10 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
         const bool last_cell = lane + 1 == ncell;
         const uint32_t nl = has_cell ? ((last_cell ? n_tot : before_next) - before) : 0u;
         const uint32_t n_slots_l = has_cell ? ((last_cell ? G : first_next) - first) : 0u;
-        // 2^ceil(log2 n) buckets (at most one key per bucket on average)
-        const uint32_t lgl = nl > 1 ? 32u - static_cast<uint32_t>(__clz(static_cast<int>(nl - 1u))) : 0u;
+        // 2^floor(log2 n) buckets: at most n per cell, so the bucket table of a
+        // group fits in CAP entries (a smaller LDS footprint keeps 16 wavefronts
+        // per CU resident)
+        const uint32_t lgl = nl ? 31u - static_cast<uint32_t>(__clz(static_cast<int>(nl))) : 0u;
         const uint32_t nbl = nl ? (1u << lgl) : 0u;
         const uint32_t calls_l = (n_slots_l + 3u) >> 2;            // Philox calls for the keys
         // one scan for bucket bases (bits 0..10), pair bases (11..19) and call bases (20..27)
@@ -522,12 +524,12 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
 
         // exclusive scan of the nb_tot bucket counts; start[nb_tot] = n_tot
         {
-            const uint32_t per = (nb_tot + kWave - 1) / kWave;   // <= 2K
+            const uint32_t per = (nb_tot + kWave - 1) / kWave;   // <= K
             const uint32_t base = lane * per;
-            uint32_t v[2 * K];
+            uint32_t v[K];
             uint32_t sum = 0;
 #pragma unroll
-            for (int t = 0; t < 2 * K; ++t) {
+            for (int t = 0; t < K; ++t) {
                 v[t] = 0;
                 if (static_cast<uint32_t>(t) < per && base + t < nb_tot) v[t] = L.sort.start[base + t];
                 sum += v[t];
@@ -535,7 +537,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
             const uint32_t inc = wave_inclusive_sum_dpp(sum);
             uint32_t run = inc - sum;
 #pragma unroll
-            for (int t = 0; t < 2 * K; ++t) {
+            for (int t = 0; t < K; ++t) {
                 if (static_cast<uint32_t>(t) < per && base + t < nb_tot) L.sort.start[base + t] = run;
                 run += v[t];
             }
