@@ -100,7 +100,6 @@ def bench_large(args):
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     ctx = sdm.Context(pop.cell, pop.xi, pop.r, pop.dV, stream=stream)
-    plan = ctx.plan()
     if args.launch:
         slots, gpw, wpb, bt, xr = (int(v) for v in args.launch.split(","))
         ctx.set_launch_config(group_slots=slots, groups_per_wave=gpw, waves_per_block=wpb,
@@ -109,6 +108,7 @@ def bench_large(args):
         best = ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=3)
         log(f"autotuned launch config {best.as_dict()}")
     cfg = ctx.launch_config().as_dict()
+    plan = ctx.plan()
     for t in range(args.warmup):
         ctx.step(pop.dt, pop.kernel, pop.seed, t)
     torch.cuda.synchronize()
