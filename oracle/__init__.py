@@ -105,6 +105,12 @@ def lib() -> ctypes.CDLL:
     L.oracle_sd_conc.restype = None
     L.oracle_max_probability.argtypes = [u32, P, P, P, P, dbl, i32, P, u64, u32, u32, P]
     L.oracle_max_probability.restype = dbl
+    L.oracle_advect_1d.argtypes = [dbl, dbl, u32, dbl, dbl]
+    L.oracle_advect_1d.restype = dbl
+    L.oracle_transport.argtypes = [u64, u32, u32, dbl, dbl, P, P, dbl, i32, P, P, P, P, P, P]
+    L.oracle_transport.restype = None
+    L.oracle_resort.argtypes = [u64, P, u32, P, P]
+    L.oracle_resort.restype = None
     _lib = L
     return L
 
@@ -189,6 +195,16 @@ def recycle_cell(xi_cell, r_cell):
     r = np.array(r_cell, dtype=np.float64)
     n = lib().oracle_recycle_cell(xi.size, _ptr(xi), _ptr(r))
     return xi, r, int(n)
+
+
+def _column(v: float, d: float, n: int) -> int:
+    """floor(v / d) clamped to [0, n - 1], as the oracle's transport computes it."""
+    f = np.floor(v / d)
+    return 0 if f < 0 else (n - 1 if f >= n else int(f))
+
+
+def advect_1d(x: float, d: float, i: int, c_l: float, c_r: float) -> float:
+    return float(lib().oracle_advect_1d(x, d, i, c_l, c_r))
 
 
 def cell_order(xi_cell: np.ndarray, seed: int, cell: int, step: int) -> np.ndarray:
@@ -287,6 +303,53 @@ class SlotState:
                                                _ptr(self.xi), _ptr(self.r), dt, kind, _ptr(p),
                                                seed, step, 0, _ptr(cm)))
         return (g, cm[:self.n_cells].copy()) if per_cell else g
+
+    def set_positions(self, x, z, nx: int, nz: int, dx: float, dz: float):
+        """Attach positions (input order) on an nx x nz grid; the cells are taken from
+        the positions and the storage is re-sorted by them (stable)."""
+        assert nx * nz == self.n_cells
+        self.grid = (int(nx), int(nz), float(dx), float(dz))
+        idx = self.id.astype(np.int64)
+        self.x = np.ascontiguousarray(np.asarray(x, dtype=np.float64)[idx])
+        self.z = np.ascontiguousarray(np.asarray(z, dtype=np.float64)[idx])
+        i = np.clip(np.floor(self.x / dx), 0, nx - 1).astype(np.uint32)
+        k = np.clip(np.floor(self.z / dz), 0, nz - 1).astype(np.uint32)
+        self._resort(i + np.uint32(nx) * k)
+
+    def _resort(self, cell):
+        order = np.zeros(max(1, cell.size), dtype=np.uint64)
+        off = np.zeros(self.n_cells + 1, dtype=np.uint64)
+        cell = np.ascontiguousarray(cell, dtype=np.uint32)
+        lib().oracle_resort(cell.size, _ptr(cell), self.n_cells, _ptr(off), _ptr(order))
+        o = order[:cell.size].astype(np.int64)
+        self.offsets = off
+        self.xi = np.ascontiguousarray(self.xi[o])
+        self.r = np.ascontiguousarray(self.r[o])
+        self.id = np.ascontiguousarray(self.id[o])
+        self.x = np.ascontiguousarray(self.x[o])
+        self.z = np.ascontiguousarray(self.z[o])
+
+    def transport(self, cx, cz, dt: float, sediment: bool = True, params=None):
+        """Advect (Courant fields cx: nz*nx, cz: (nz+1)*nx, either None), sediment,
+        drop leavers, re-sort by cell."""
+        nx, nz, dx, dz = self.grid
+        p = _params(params)
+        cxa = None if cx is None else np.ascontiguousarray(cx, dtype=np.float64)
+        cza = None if cz is None else np.ascontiguousarray(cz, dtype=np.float64)
+        cell = np.zeros(max(1, self.xi.size), dtype=np.uint32)
+        lib().oracle_transport(self.xi.size, nx, nz, dx, dz,
+                               None if cxa is None else _ptr(cxa),
+                               None if cza is None else _ptr(cza), dt, 1 if sediment else 0,
+                               _ptr(p), _ptr(self.x), _ptr(self.z), _ptr(self.xi),
+                               _ptr(self.r), _ptr(cell))
+        self._resort(cell[:self.xi.size])
+
+    def positions_input_order(self):
+        x = np.empty_like(self.x)
+        z = np.empty_like(self.z)
+        x[self.id.astype(np.int64)] = self.x
+        z[self.id.astype(np.int64)] = self.z
+        return x, z
 
     def input_order(self):
         """(xi, r) scattered back to input order."""

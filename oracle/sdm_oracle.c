@@ -35,6 +35,12 @@
  *     multiplicity left on the first pair member when multiplicities are
  *     equal; recycling (ORACLE_RULE_RECYCLE) runs within each cell at the
  *     start of every step, before the pairing, as in oracle_recycle_cell;
+ *   - transport: both directions use the Courant numbers of the cell the
+ *     particle is in at time level n (dimension-split, not sequential), the
+ *     sedimentation fall is applied after the advection, x wraps once per step,
+ *     a particle leaving [0, nz dz) gets multiplicity 0 and is clamped into
+ *     the boundary row, and the storage is re-sorted by cell keeping the old
+ *     storage order within a cell;
  *   - moments count live super-droplets only, the radius range is closed at
  *     both ends, and rho_d defaults to 1 (moments per unit volume) when no
  *     dry-air density is given; the summation order is fixed (see
@@ -626,4 +632,94 @@ double oracle_max_probability(uint32_t n_cells, const uint64_t *offsets, const d
     }
     free(order);
     return pmax;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transport (Sect. 5.1: advection and sedimentation of the particles)       */
+/* ------------------------------------------------------------------------ */
+/* A 2D domain of nx x nz cells of size dx x dz, periodic in x, cell index    */
+/* c = i + nx k with i = floor(x / dx), k = floor(z / dz) (clamped to the     */
+/* grid).  Courant numbers on an Arakawa-C grid: cx[k nx + i] on the left     */
+/* edge of cell (i, k) (edge nx of a row is edge 0), cz[k nx + i] on the      */
+/* bottom edge of cell (i, k), k = 0 .. nz.                                   */
+static uint32_t oracle_column(double x, double dx, uint32_t nx)
+{
+    double f = floor(x / dx);
+    if (f < 0.0) return 0u;
+    if (f >= (double)nx) return nx - 1u;
+    return (uint32_t)f;
+}
+
+/* Backward-Euler advection in one dimension with the linear interpolation of
+ * the Courant number between the edges of the particle's cell at time level
+ * n, solved analytically: x' = (x + d (C_l - i dC)) / (1 - dC), dC = C_r - C_l. */
+double oracle_advect_1d(double x, double d, uint32_t i, double c_l, double c_r)
+{
+    double dC = c_r - c_l;
+    double num = x + d * (c_l - (double)i * dC);
+    return num / (1.0 - dC);
+}
+
+/* Move every super-droplet (storage order): advection by the Courant fields
+ * (either may be NULL for no flow in that direction), then, if sediment is set,
+ * the fall by v_t(r) dt (explicit Euler).  x wraps periodically (a position
+ * that rounds to the domain width becomes 0).  A super-droplet whose z leaves
+ * [0, nz dz) gets multiplicity 0 and z clamped to 0 (below) or to the bottom
+ * edge of the top row (above).  cell_out receives the new cell index. */
+void oracle_transport(uint64_t n, uint32_t nx, uint32_t nz, double dx, double dz,
+                      const double *cx, const double *cz, double dt, int sediment,
+                      const double *params, double *x, double *z, uint64_t *xi,
+                      const double *r, uint32_t *cell_out)
+{
+    double Lx = (double)nx * dx;
+    double Lz = (double)nz * dz;
+    for (uint64_t s = 0; s < n; ++s) {
+        uint32_t i = oracle_column(x[s], dx, nx);
+        uint32_t k = oracle_column(z[s], dz, nz);
+        double xn = x[s], zn = z[s];
+        if (cx) {
+            double cl = cx[(uint64_t)k * nx + i];
+            double cr = cx[(uint64_t)k * nx + (i + 1u == nx ? 0u : i + 1u)];
+            xn = oracle_advect_1d(x[s], dx, i, cl, cr);
+        }
+        if (cz) {
+            double cb = cz[(uint64_t)k * nx + i];
+            double ct = cz[(uint64_t)(k + 1u) * nx + i];
+            zn = oracle_advect_1d(z[s], dz, k, cb, ct);
+        }
+        if (sediment) zn = zn - oracle_terminal_velocity(params, r[s]) * dt;
+        if (xn < 0.0) {
+            xn = xn + Lx;
+            if (xn >= Lx) xn = 0.0;
+        } else if (xn >= Lx) {
+            xn = xn - Lx;
+        }
+        if (zn < 0.0) {
+            xi[s] = 0;
+            zn = 0.0;
+        } else if (zn >= Lz) {
+            xi[s] = 0;
+            zn = (double)(nz - 1u) * dz;
+        }
+        x[s] = xn;
+        z[s] = zn;
+        cell_out[s] = oracle_column(xn, dx, nx) + nx * oracle_column(zn, dz, nz);
+    }
+}
+
+/* Stable counting sort of the storage slots by cell: order[j] = the old slot
+ * that moves to new slot j; offsets (n_cells + 1) of the new layout. */
+void oracle_resort(uint64_t n, const uint32_t *cell, uint32_t n_cells, uint64_t *offsets,
+                   uint64_t *order)
+{
+    uint64_t *fill = (uint64_t *)calloc((size_t)n_cells + 1u, sizeof(uint64_t));
+    memset(offsets, 0, sizeof(uint64_t) * ((size_t)n_cells + 1u));
+    for (uint64_t s = 0; s < n; ++s) offsets[cell[s] + 1u] += 1u;
+    for (uint32_t c = 0; c < n_cells; ++c) offsets[c + 1u] += offsets[c];
+    for (uint64_t s = 0; s < n; ++s) {
+        uint32_t c = cell[s];
+        order[offsets[c] + fill[c]] = s;
+        fill[c] += 1u;
+    }
+    free(fill);
 }

@@ -214,3 +214,37 @@ def tiny_cells(seed: int, n_cells: int, max_per_cell: int, xi_max: int = 1000,
     r = np.exp(g.uniform(np.log(r_lo), np.log(r_hi), n))
     dV = g.uniform(1.0, 100.0, n_cells)
     return Population("tiny_cells", cell, xi, r, dV, "geometric", 1.0, 1, seed)
+
+
+# ---------------------------------------------------------------- transport inputs
+def positions_in_cells(pop: Population, nx: int, nz: int, dx: float, dz: float,
+                       seed: int) -> tuple:
+    """Positions uniform within each SD's cell (cell = i + nx k), input order."""
+    g = _rng(seed ^ 0x5EED)
+    i = (pop.cell % nx).astype(np.float64)
+    k = (pop.cell // nx).astype(np.float64)
+    x = (i + g.random(pop.n_sd)) * dx
+    z = (k + g.random(pop.n_sd)) * dz
+    # keep every position strictly inside its cell
+    x = np.minimum(x, np.nextafter((i + 1.0) * dx, 0.0))
+    z = np.minimum(z, np.nextafter((k + 1.0) * dz, 0.0))
+    return x, z
+
+
+def eddy_courant(nx: int, nz: int, dx: float, dz: float, dt: float,
+                 w_max: float = 0.6) -> tuple:
+    """Courant numbers of the single-eddy kinematic flow on an Arakawa-C grid.
+
+    Stream function psi = -w_max X/pi sin(pi z/Z) cos(2 pi x/X) (X = nx dx,
+    Z = nz dz) at the cell corners, constant dry-air density; u = -d psi/dz on the
+    x-edges and w = d psi/dx on the z-edges by differences of corner values, so the
+    discrete divergence vanishes to round-off.  Returns (cx, cz): cx[k nx + i] on the
+    left edge of cell (i, k), cz[k nx + i] on its bottom edge (k = 0..nz)."""
+    X, Z = nx * dx, nz * dz
+    xc = np.arange(nx + 1) * dx
+    zc = np.arange(nz + 1) * dz
+    psi = -w_max * X / np.pi * np.sin(np.pi * zc[:, None] / Z) * np.cos(2 * np.pi * xc[None, :] / X)
+    u = -(psi[1:, :nx] - psi[:-1, :nx]) / dz           # (nz, nx) on x-edges
+    w = (psi[:, 1:] - psi[:, :-1]) / dx                 # (nz + 1, nx) on z-edges
+    return (np.ascontiguousarray((u * dt / dx).ravel()),
+            np.ascontiguousarray((w * dt / dz).ravel()))
