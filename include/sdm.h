@@ -137,7 +137,7 @@ sdm_status sdm_get_stats(sdm_ctx *ctx, uint64_t *pair_tests, uint64_t *collision
 
 /* Storage-order views for diagnostics: slot offsets (dev uint32[n_cells+1])
  * and slot->input-index map (dev uint32[n_sd]).  Pointers into the workspace,
- * valid while the context lives. */
+ * valid while the context lives and until the next transport step. */
 sdm_status sdm_get_layout(sdm_ctx *ctx, const uint32_t **offsets, const uint32_t **input_index);
 
 /* Compute, without changing the state, the pairing order step `step` would
@@ -239,6 +239,53 @@ sdm_status sdm_coalesce_substeps(sdm_ctx *ctx, double dt, uint32_t n_substeps, s
 sdm_status sdm_coalesce_adaptive(sdm_ctx *ctx, double dt, double p_limit, uint32_t max_substeps,
                                  sdm_kernel kernel, uint64_t seed, uint64_t first_step,
                                  uint32_t *substeps_out);
+
+/* ------------------------------------------------------------------------ */
+/* Particle transport (Sect. 5.1, advection and sedimentation).  A context   */
+/* whose cells form an nx x nz grid (cell = i + nx k) can carry positions:   */
+/* each transport step moves every super-droplet and re-sorts the storage by */
+/* cell, so the next coalescence step pairs particles in their new cells.    */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of the caller-owned device workspace sdm_transport_attach needs
+ * (56 B per super-droplet: positions, their re-sort targets, and re-sort
+ * targets of xi, r and the input index). */
+size_t sdm_transport_workspace_bytes(uint64_t n_sd);
+
+/* Attach positions: x_in, z_in (dev double[n_sd], input order) inside
+ * [0, nx dx) x [0, nz dz); nx * nz must equal n_cells.  From here on a
+ * super-droplet's cell is i + nx k with i = floor(x / dx), k = floor(z / dz)
+ * (clamped to the grid), and the storage is re-sorted by those cells at once
+ * (stable in the present storage order), which also rebuilds the launch plan.
+ * The workspace (256-byte aligned) must stay allocated while the context lives.
+ * Synchronises.  Errors: SDM_EINVAL (grid, spacing, NULL or out-of-domain
+ * positions, workspace), SDM_ENOMEM (workspace too small), SDM_ESTATE (already
+ * attached). */
+sdm_status sdm_transport_attach(sdm_ctx *ctx, void *workspace, size_t ws_bytes, uint32_t nx,
+                                uint32_t nz, double dx, double dz, const double *x_in,
+                                const double *z_in);
+
+/* One transport step of length dt.  cx (dev double[nz * nx]) holds the Courant
+ * numbers u dt / dx on the left edge of every cell (the right edge of cell nx-1
+ * of a row is edge 0: periodic in x), cz (dev double[(nz + 1) * nx]) the
+ * numbers w dt / dz on the bottom edge of every cell (row nz is the top
+ * boundary); either may be NULL (no flow in that direction).  Each particle
+ * uses the edges of its cell at the start of the step in both directions:
+ * x' = (x + dx (C_l - i dC)) / (1 - dC), dC = C_r - C_l (backward Euler with
+ * the linearly interpolated Courant number, solved analytically), likewise in
+ * z.  With sediment != 0 it then falls by v_t(r) dt (the kernel parameters'
+ * terminal velocity, explicit Euler).  x wraps periodically; a particle whose z
+ * leaves [0, nz dz) gets xi = 0 and is clamped into the boundary row.  The
+ * storage is then re-sorted by cell (stable) and the plan rebuilt; pointers
+ * from sdm_get_layout change.  Synchronises.  Errors: SDM_ESTATE (no transport
+ * attached), SDM_EINVAL (dt, or Courant numbers not finite or with
+ * C_r - C_l >= 1 in some cell). */
+sdm_status sdm_transport_step(sdm_ctx *ctx, const double *cx, const double *cz, double dt,
+                              int sediment);
+
+/* Positions in input order: x_out, z_out (dev double[n_sd]), either may be
+ * NULL.  Synchronises.  Errors: SDM_ESTATE (no transport attached). */
+sdm_status sdm_transport_get_positions(sdm_ctx *ctx, double *x_out, double *z_out);
 
 /* Launch plan of a context: number of wave-tier groups (runs of consecutive
  * cells processed by one wavefront), cells in them, and cells handled one

@@ -1,6 +1,6 @@
 // context.hip -- the single-run C ABI: sdm_init / sdm_coalesce_step and the
 // state, counter, layout, plan and permutation queries of a context.
-#include "runtime.hpp"
+#include "context.hpp"
 #include "diag_kernels.hpp"
 #include "recycle_kernels.hpp"
 
@@ -9,37 +9,6 @@
 #include <cstring>
 
 using namespace sdm;
-
-struct sdm_ctx {
-    hipStream_t stream = nullptr;
-    uint64_t n_sd = 0;
-    uint32_t n_cells = 0;
-    sdm_kernel_params params{};
-    // device arrays (inside the caller's workspace)
-    uint64_t* xi = nullptr;
-    double* r = nullptr;
-    uint32_t* id = nullptr;
-    uint32_t* offsets = nullptr;
-    double* dV = nullptr;
-    uint32_t* group_begin = nullptr;
-    uint32_t* group_end = nullptr;
-    uint32_t* block_items = nullptr;
-    GridArrays grid;
-    unsigned long long* stats = nullptr;
-    unsigned int* err = nullptr;
-    uint32_t* probe_order = nullptr;
-    uint32_t* probe_nlive = nullptr;
-    unsigned long long* probe_max = nullptr;
-    uint64_t* scr_kv = nullptr;
-    uint64_t* scr_tmp = nullptr;
-    uint32_t* scr_pos = nullptr;
-    uint32_t* scr_cnt = nullptr;
-    // plan
-    std::vector<uint32_t> sizes;   // storage slots per cell (host copy)
-    uint32_t n_groups = 0, n_wave_cells = 0, n_block = 0;
-    LaunchShape shape;
-    uint32_t rules = 0;   // sdm_rule flags applied by every step
-};
 
 namespace {
 
@@ -155,6 +124,13 @@ sdm_status upload_plan(sdm_ctx* x)
 
 }  // namespace
 
+namespace sdm {
+sdm_status ctx_replan(sdm_ctx* x)
+{
+    return upload_plan(x);
+}
+}  // namespace sdm
+
 extern "C" size_t sdm_workspace_bytes(uint64_t n_sd, uint32_t n_cells)
 {
     return layout(nullptr, 0, n_sd, n_cells).bytes;
@@ -243,6 +219,7 @@ extern "C" sdm_status sdm_init(sdm_ctx** out, void* stream, void* workspace, siz
     x->scr_tmp = L.scr_tmp;
     x->scr_pos = L.scr_pos;
     x->scr_cnt = L.scr_cnt;
+    x->sort = L.sort;
     x->sizes.resize(n_cells);
     for (uint32_t c = 0; c < n_cells; ++c) x->sizes[c] = off[c + 1] - off[c];
     const sdm_status st = upload_plan(x);

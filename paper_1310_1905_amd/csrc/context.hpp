@@ -1,0 +1,67 @@
+// context.hpp -- the state of a single-run context, shared by the files that
+// implement its C ABI (context.hip: steps and queries; transport.hip: particle
+// transport between cells).
+#pragma once
+
+#include "runtime.hpp"
+
+#include <memory>
+
+namespace sdm {
+
+// Positions and grid of a context with transport attached; every array is in
+// storage order and lives in the caller's transport workspace.
+struct TransportState {
+    uint32_t nx = 0, nz = 0;
+    double dx = 0.0, dz = 0.0;
+    double* x = nullptr;        // positions
+    double* z = nullptr;
+    double* x_alt = nullptr;    // gather targets of the re-sort (swapped with the live arrays)
+    double* z_alt = nullptr;
+    uint64_t* xi_alt = nullptr;
+    double* r_alt = nullptr;
+    uint32_t* id_alt = nullptr;
+    uint32_t* cell = nullptr;   // new cell of every slot
+};
+
+}  // namespace sdm
+
+struct sdm_ctx {
+    hipStream_t stream = nullptr;
+    uint64_t n_sd = 0;
+    uint32_t n_cells = 0;
+    sdm_kernel_params params{};
+    // device arrays (inside the caller's workspace)
+    uint64_t* xi = nullptr;
+    double* r = nullptr;
+    uint32_t* id = nullptr;
+    uint32_t* offsets = nullptr;
+    double* dV = nullptr;
+    uint32_t* group_begin = nullptr;
+    uint32_t* group_end = nullptr;
+    uint32_t* block_items = nullptr;
+    sdm::GridArrays grid;
+    unsigned long long* stats = nullptr;
+    unsigned int* err = nullptr;
+    uint32_t* probe_order = nullptr;
+    uint32_t* probe_nlive = nullptr;
+    unsigned long long* probe_max = nullptr;
+    uint64_t* scr_kv = nullptr;
+    uint64_t* scr_tmp = nullptr;
+    uint32_t* scr_pos = nullptr;
+    uint32_t* scr_cnt = nullptr;
+    // plan
+    std::vector<uint32_t> sizes;   // storage slots per cell (host copy)
+    uint32_t n_groups = 0, n_wave_cells = 0, n_block = 0;
+    sdm::LaunchShape shape;
+    uint32_t rules = 0;   // sdm_rule flags applied by every step
+    // admission sort scratch (shares the step scratch region; reused by transport)
+    sdm::SortScratch sort{};
+    // particle positions and the transport buffers, once attached
+    std::unique_ptr<sdm::TransportState> transport;
+};
+
+namespace sdm {
+// Rebuild the launch plan from x->sizes and upload it (synchronises).
+sdm_status ctx_replan(sdm_ctx* x);
+}  // namespace sdm

@@ -73,11 +73,19 @@ __global__ void k_keys_iota(uint64_t n, const uint32_t* cell, uint32_t key_add, 
     }
 }
 
-__global__ void k_count_cells(uint64_t n, const uint32_t* cell, uint32_t* counts)
+// Slot offsets from the cell indices sorted ascending: offsets[c] = first j with
+// keys[j] >= c, for c = 0..n_cells (so offsets[n_cells] = n).  Element j writes
+// the offsets of the cells that start at j, so every entry is written once and
+// no atomics are needed.
+__global__ void k_offsets_from_sorted(uint64_t n, const uint32_t* keys, uint32_t n_cells,
+                                      uint32_t* offsets)
 {
-    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
-        atomicAdd(&counts[cell[i]], 1u);
+    for (uint64_t j = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; j <= n;
+         j += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint64_t lo = j == 0 ? 0u : static_cast<uint64_t>(keys[j - 1]) + 1u;
+        const uint64_t hi = j == n ? static_cast<uint64_t>(n_cells) : keys[j];
+        for (uint64_t c = lo; c <= hi; ++c) offsets[c] = static_cast<uint32_t>(j);
+    }
 }
 
 // ---------------------------------------------------------------------------

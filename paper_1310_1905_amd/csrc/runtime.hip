@@ -37,7 +37,6 @@ void carve_sort_scratch(Carver& c, uint64_t n_sd, uint32_t n_cells, SortScratch*
     s->vals_b = c.take<uint32_t>(n_sd);
     s->radix_counts = c.take<uint32_t>(radix_entries);
     s->tile_sums = c.take<uint32_t>((longest + kScanTile - 1) / kScanTile + 1);
-    s->cell_counts = c.take<uint32_t>(static_cast<uint64_t>(n_cells) + 1);
 }
 
 sdm_status scan_exclusive(hipStream_t s, const uint32_t* in, uint32_t* out, uint64_t n,
@@ -89,6 +88,12 @@ sdm_status sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, const d
         return SDM_EINVAL;
     }
 
+    return radix_sort_by_cell(s, n, cell, n_cells, scr, offsets, order);
+}
+
+sdm_status radix_sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, uint32_t n_cells,
+                              SortScratch& scr, uint32_t* offsets, const uint32_t** order)
+{
     // stable LSD radix sort of (cell, input index)
     uint32_t* ka = scr.keys_a;
     uint32_t* va = scr.vals_a;
@@ -116,16 +121,10 @@ sdm_status sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, const d
     }
     *order = va;
 
-    // slot offsets = exclusive scan of the per-cell counts
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(uint64_t(n_cells) + 1, 256, 4096)), dim3(256), 0,
-                       s, scr.cell_counts, uint64_t(n_cells) + 1, 0u);
+    // slot offsets from the sorted cell indices (ka)
+    hipLaunchKernelGGL(k_offsets_from_sorted, dim3(grid_for(n + 1, 256, 8192)), dim3(256), 0, s, n,
+                       ka, n_cells, offsets);
     SDM_LAUNCHED();
-    if (n > 0) {
-        hipLaunchKernelGGL(k_count_cells, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, cell,
-                           scr.cell_counts);
-        SDM_LAUNCHED();
-    }
-    SDM_TRY(scan_exclusive(s, scr.cell_counts, offsets, uint64_t(n_cells) + 1, scr.tile_sums));
     return SDM_OK;
 }
 

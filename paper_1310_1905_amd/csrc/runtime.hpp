@@ -96,7 +96,6 @@ struct SortScratch {
     uint32_t* vals_b;
     uint32_t* radix_counts;   // kRadixDigits * tiles
     uint32_t* tile_sums;      // scan tile sums
-    uint32_t* cell_counts;    // n_cells + 1
 };
 void carve_sort_scratch(Carver& c, uint64_t n_sd, uint32_t n_cells, SortScratch* s);
 
@@ -110,6 +109,12 @@ sdm_status scan_exclusive(hipStream_t s, const uint32_t* in, uint32_t* out, uint
 sdm_status sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, const double* r,
                         uint32_t n_cells, const double* dV, SortScratch& scr,
                         uint32_t* offsets, unsigned int* err_dev, const uint32_t** order);
+
+// The sort alone (no validation, no synchronisation): *order (a scratch array)
+// holds, for each new slot, the index of the element that moves there (stable),
+// offsets[0..n_cells] the slot offsets.  Cell indices must be < n_cells.
+sdm_status radix_sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, uint32_t n_cells,
+                              SortScratch& scr, uint32_t* offsets, const uint32_t** order);
 
 // Launch shape of the step kernels (none of it changes a result).
 struct LaunchShape {

@@ -1,0 +1,349 @@
+// transport.hip -- particle transport between cells (Sect. 5.1: advection by
+// the Eulerian Courant field with the backward-Euler scheme and its analytic
+// solution on an Arakawa-C grid, periodic in x; sedimentation by explicit
+// Euler; particles leaving the domain flagged with zero multiplicity),
+// followed by the stable re-sort of the storage by cell.
+#include "context.hpp"
+
+#include <cmath>
+
+using namespace sdm;
+
+#pragma clang fp contract(off)
+
+namespace {
+
+constexpr unsigned int kErrCourant = 1u;
+constexpr unsigned int kErrPosition = 2u;
+
+// floor(v / d) clamped to [0, n - 1]
+__device__ __forceinline__ uint32_t column_of(double v, double d, uint32_t n)
+{
+    const double f = floor(v / d);
+    if (f < 0.0) return 0u;
+    if (f >= static_cast<double>(n)) return n - 1u;
+    return static_cast<uint32_t>(f);
+}
+
+// x' = (x + d (C_l - i dC)) / (1 - dC), dC = C_r - C_l: backward Euler with the
+// Courant number interpolated linearly between the edges of the cell of time level n.
+__device__ __forceinline__ double advect_1d(double x, double d, uint32_t i, double c_l, double c_r)
+{
+    const double dC = c_r - c_l;
+    const double num = x + d * (c_l - static_cast<double>(i) * dC);
+    return num / (1.0 - dC);
+}
+
+__global__ void k_validate_courant(uint32_t nx, uint32_t nz, const double* cx, const double* cz,
+                                   unsigned int* err)
+{
+    const uint64_t n = static_cast<uint64_t>(nx) * nz;
+    for (uint64_t c = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; c < n;
+         c += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint32_t i = static_cast<uint32_t>(c % nx), k = static_cast<uint32_t>(c / nx);
+        bool bad = false;
+        if (cx) {
+            const double l = cx[static_cast<uint64_t>(k) * nx + i];
+            const double r = cx[static_cast<uint64_t>(k) * nx + (i + 1u == nx ? 0u : i + 1u)];
+            bad |= !isfinite(l) || !isfinite(r) || !(1.0 - (r - l) > 0.0);
+        }
+        if (cz) {
+            const double b = cz[static_cast<uint64_t>(k) * nx + i];
+            const double t = cz[static_cast<uint64_t>(k + 1u) * nx + i];
+            bad |= !isfinite(b) || !isfinite(t) || !(1.0 - (t - b) > 0.0);
+        }
+        if (bad) atomicOr(err, kErrCourant);
+    }
+}
+
+// Positions from input order to storage order, checked to lie in the domain.
+__global__ void k_positions_in(uint64_t n, const uint32_t* id, const double* x_in,
+                               const double* z_in, double* x, double* z, double Lx, double Lz,
+                               unsigned int* err)
+{
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const double xv = x_in[id[s]], zv = z_in[id[s]];
+        if (!(xv >= 0.0 && xv < Lx && zv >= 0.0 && zv < Lz)) atomicOr(err, kErrPosition);
+        x[s] = xv;
+        z[s] = zv;
+    }
+}
+
+__global__ void k_cells_of(uint64_t n, const double* x, const double* z, uint32_t nx, uint32_t nz,
+                           double dx, double dz, uint32_t* cell)
+{
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        cell[s] = column_of(x[s], dx, nx) + nx * column_of(z[s], dz, nz);
+}
+
+// One transport step of every super-droplet (storage order).
+__global__ void k_transport(uint64_t n, uint32_t nx, uint32_t nz, double dx, double dz,
+                            const double* __restrict__ cx, const double* __restrict__ cz,
+                            double dt, int sediment, KernelParams kp, double Lx, double Lz,
+                            double* __restrict__ x, double* __restrict__ z,
+                            uint64_t* __restrict__ xi, const double* __restrict__ r,
+                            uint32_t* __restrict__ cell)
+{
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const double x0 = x[s], z0 = z[s];
+        const uint32_t i = column_of(x0, dx, nx);
+        const uint32_t k = column_of(z0, dz, nz);
+        double xn = x0, zn = z0;
+        if (cx) {
+            const double l = cx[static_cast<uint64_t>(k) * nx + i];
+            const double rr = cx[static_cast<uint64_t>(k) * nx + (i + 1u == nx ? 0u : i + 1u)];
+            xn = advect_1d(x0, dx, i, l, rr);
+        }
+        if (cz) {
+            const double b = cz[static_cast<uint64_t>(k) * nx + i];
+            const double t = cz[static_cast<uint64_t>(k + 1u) * nx + i];
+            zn = advect_1d(z0, dz, k, b, t);
+        }
+        if (sediment) zn = zn - terminal_velocity(kp, r[s]) * dt;
+        if (xn < 0.0) {
+            xn = xn + Lx;
+            if (xn >= Lx) xn = 0.0;
+        } else if (xn >= Lx) {
+            xn = xn - Lx;
+        }
+        if (zn < 0.0) {
+            xi[s] = 0;
+            zn = 0.0;
+        } else if (zn >= Lz) {
+            xi[s] = 0;
+            zn = static_cast<double>(nz - 1u) * dz;
+        }
+        x[s] = xn;
+        z[s] = zn;
+        cell[s] = column_of(xn, dx, nx) + nx * column_of(zn, dz, nz);
+    }
+}
+
+__global__ void k_gather_sd(uint64_t n, const uint32_t* __restrict__ order,
+                            const uint64_t* __restrict__ xi, const double* __restrict__ r,
+                            const uint32_t* __restrict__ id, const double* __restrict__ x,
+                            const double* __restrict__ z, uint64_t* __restrict__ xi_o,
+                            double* __restrict__ r_o, uint32_t* __restrict__ id_o,
+                            double* __restrict__ x_o, double* __restrict__ z_o)
+{
+    for (uint64_t j = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; j < n;
+         j += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint32_t s = order[j];
+        xi_o[j] = xi[s];
+        r_o[j] = r[s];
+        id_o[j] = id[s];
+        x_o[j] = x[s];
+        z_o[j] = z[s];
+    }
+}
+
+__global__ void k_positions_out(uint64_t n, const uint32_t* id, const double* x, const double* z,
+                                double* x_out, double* z_out)
+{
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        if (x_out) x_out[id[s]] = x[s];
+        if (z_out) z_out[id[s]] = z[s];
+    }
+}
+
+struct TransportLayout {
+    double *x, *z, *x_alt, *z_alt, *r_alt;
+    uint64_t* xi_alt;
+    uint32_t *id_alt, *cell;
+    size_t bytes;
+};
+
+TransportLayout transport_layout(void* ws, size_t ws_bytes, uint64_t n)
+{
+    Carver cv(ws, ws_bytes);
+    TransportLayout L{};
+    L.x = cv.take<double>(n);
+    L.z = cv.take<double>(n);
+    L.x_alt = cv.take<double>(n);
+    L.z_alt = cv.take<double>(n);
+    L.xi_alt = cv.take<uint64_t>(n);
+    L.r_alt = cv.take<double>(n);
+    L.id_alt = cv.take<uint32_t>(n);
+    L.cell = cv.take<uint32_t>(n);
+    L.bytes = cv.used();
+    return L;
+}
+
+sdm_status read_error(sdm_ctx* x, unsigned int* out)
+{
+    SDM_HIP(hipMemcpyAsync(out, x->err, sizeof(unsigned int), hipMemcpyDeviceToHost, x->stream));
+    SDM_HIP(hipStreamSynchronize(x->stream));
+    return SDM_OK;
+}
+
+sdm_status clear_error(sdm_ctx* x)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, x->stream,
+                       reinterpret_cast<uint32_t*>(x->err), uint64_t(1), 0u);
+    SDM_LAUNCHED();
+    return SDM_OK;
+}
+
+// Stable re-sort of the storage by T.cell, then a new launch plan.
+sdm_status resort(sdm_ctx* x)
+{
+    TransportState& T = *x->transport;
+    const uint64_t n = x->n_sd;
+    const uint32_t* order = nullptr;
+    SDM_TRY(radix_sort_by_cell(x->stream, n, T.cell, x->n_cells, x->sort, x->offsets, &order));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_gather_sd, dim3(grid_for(n, 256, 8192)), dim3(256), 0, x->stream, n,
+                           order, x->xi, x->r, x->id, T.x, T.z, T.xi_alt, T.r_alt, T.id_alt,
+                           T.x_alt, T.z_alt);
+        SDM_LAUNCHED();
+        std::swap(x->xi, T.xi_alt);
+        std::swap(x->r, T.r_alt);
+        std::swap(x->id, T.id_alt);
+        std::swap(T.x, T.x_alt);
+        std::swap(T.z, T.z_alt);
+    }
+    std::vector<uint32_t> off(uint64_t(x->n_cells) + 1);
+    SDM_HIP(hipMemcpyAsync(off.data(), x->offsets, off.size() * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, x->stream));
+    SDM_HIP(hipStreamSynchronize(x->stream));
+    for (uint32_t c = 0; c < x->n_cells; ++c) x->sizes[c] = off[c + 1] - off[c];
+    return ctx_replan(x);
+}
+
+sdm_status check_attached(const sdm_ctx* x)
+{
+    if (!x) {
+        set_error("context is NULL");
+        return SDM_EINVAL;
+    }
+    if (!x->transport) {
+        set_error("no transport attached (sdm_transport_attach)");
+        return SDM_ESTATE;
+    }
+    return SDM_OK;
+}
+
+}  // namespace
+
+extern "C" size_t sdm_transport_workspace_bytes(uint64_t n_sd)
+{
+    return transport_layout(nullptr, 0, n_sd).bytes;
+}
+
+extern "C" sdm_status sdm_transport_attach(sdm_ctx* x, void* workspace, size_t ws_bytes,
+                                           uint32_t nx, uint32_t nz, double dx, double dz,
+                                           const double* x_in, const double* z_in)
+{
+    if (!x) {
+        set_error("context is NULL");
+        return SDM_EINVAL;
+    }
+    if (x->transport) {
+        set_error("transport is already attached");
+        return SDM_ESTATE;
+    }
+    if (nx == 0 || nz == 0 || static_cast<uint64_t>(nx) * nz != x->n_cells) {
+        set_error("the grid (%u x %u) must have exactly n_cells = %u cells", nx, nz, x->n_cells);
+        return SDM_EINVAL;
+    }
+    if (!(dx > 0.0) || !(dz > 0.0) || !std::isfinite(dx) || !std::isfinite(dz)) {
+        set_error("dx and dz must be finite and > 0");
+        return SDM_EINVAL;
+    }
+    if (x->n_sd > 0 && (!x_in || !z_in)) {
+        set_error("positions must be non-NULL");
+        return SDM_EINVAL;
+    }
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u)) {
+        set_error("workspace must be non-NULL and 256-byte aligned");
+        return SDM_EINVAL;
+    }
+    const TransportLayout L = transport_layout(workspace, ws_bytes, x->n_sd);
+    if (L.bytes > ws_bytes) {
+        set_error("transport workspace has %zu bytes, %zu needed", ws_bytes, L.bytes);
+        return SDM_ENOMEM;
+    }
+    const uint64_t n = x->n_sd;
+    const double Lx = static_cast<double>(nx) * dx, Lz = static_cast<double>(nz) * dz;
+    SDM_TRY(clear_error(x));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_positions_in, dim3(grid_for(n, 256, 8192)), dim3(256), 0, x->stream,
+                           n, x->id, x_in, z_in, L.x, L.z, Lx, Lz, x->err);
+        SDM_LAUNCHED();
+    }
+    unsigned int err = 0;
+    SDM_TRY(read_error(x, &err));
+    if (err & kErrPosition) {
+        set_error("positions must be finite and inside [0, nx dx) x [0, nz dz)");
+        return SDM_EINVAL;
+    }
+    auto T = std::make_unique<TransportState>();
+    T->nx = nx;
+    T->nz = nz;
+    T->dx = dx;
+    T->dz = dz;
+    T->x = L.x;
+    T->z = L.z;
+    T->x_alt = L.x_alt;
+    T->z_alt = L.z_alt;
+    T->xi_alt = L.xi_alt;
+    T->r_alt = L.r_alt;
+    T->id_alt = L.id_alt;
+    T->cell = L.cell;
+    x->transport = std::move(T);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_cells_of, dim3(grid_for(n, 256, 8192)), dim3(256), 0, x->stream, n,
+                           L.x, L.z, nx, nz, dx, dz, L.cell);
+        SDM_LAUNCHED();
+    }
+    return resort(x);
+}
+
+extern "C" sdm_status sdm_transport_step(sdm_ctx* x, const double* cx, const double* cz, double dt,
+                                         int sediment)
+{
+    SDM_TRY(check_attached(x));
+    if (!(dt > 0.0) || !std::isfinite(dt)) {
+        set_error("dt must be finite and > 0");
+        return SDM_EINVAL;
+    }
+    TransportState& T = *x->transport;
+    if (cx || cz) {
+        SDM_TRY(clear_error(x));
+        hipLaunchKernelGGL(k_validate_courant, dim3(grid_for(x->n_cells, 256, 4096)), dim3(256), 0,
+                           x->stream, T.nx, T.nz, cx, cz, x->err);
+        SDM_LAUNCHED();
+        unsigned int err = 0;
+        SDM_TRY(read_error(x, &err));
+        if (err & kErrCourant) {
+            set_error("Courant numbers must be finite with C_right - C_left < 1 in every cell");
+            return SDM_EINVAL;
+        }
+    }
+    const uint64_t n = x->n_sd;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_transport, dim3(grid_for(n, 256, 8192)), dim3(256), 0, x->stream, n,
+                           T.nx, T.nz, T.dx, T.dz, cx, cz, dt, sediment ? 1 : 0, to_kp(x->params),
+                           static_cast<double>(T.nx) * T.dx, static_cast<double>(T.nz) * T.dz,
+                           T.x, T.z, x->xi, x->r, T.cell);
+        SDM_LAUNCHED();
+    }
+    return resort(x);
+}
+
+extern "C" sdm_status sdm_transport_get_positions(sdm_ctx* x, double* x_out, double* z_out)
+{
+    SDM_TRY(check_attached(x));
+    const uint64_t n = x->n_sd;
+    if (n > 0 && (x_out || z_out)) {
+        hipLaunchKernelGGL(k_positions_out, dim3(grid_for(n, 256, 8192)), dim3(256), 0, x->stream,
+                           n, x->id, x->transport->x, x->transport->z, x_out, z_out);
+        SDM_LAUNCHED();
+    }
+    SDM_HIP(hipStreamSynchronize(x->stream));
+    return SDM_OK;
+}

@@ -80,6 +80,10 @@ def lib() -> ctypes.CDLL:
         "sdm_get_rules": (ctypes.c_int, [_P, _P]),
         "sdm_recycle": (ctypes.c_int, [_P]),
         "sdm_get_recycled": (ctypes.c_int, [_P, _P]),
+        "sdm_transport_workspace_bytes": (_sz, [_u64]),
+        "sdm_transport_attach": (ctypes.c_int, [_P, _P, _sz, _u32, _u32, _dbl, _dbl, _P, _P]),
+        "sdm_transport_step": (ctypes.c_int, [_P, _P, _P, _dbl, ctypes.c_int]),
+        "sdm_transport_get_positions": (ctypes.c_int, [_P, _P, _P]),
         "sdm_diag_sd_conc": (ctypes.c_int, [_P, _P]),
         "sdm_diag_moments": (ctypes.c_int, [_P, _u32, _dbl, _dbl, _P, _P]),
         "sdm_probe_probability": (ctypes.c_int, [_P, _dbl, ctypes.c_int, _u64, _u64, _P, _P]),
@@ -187,6 +191,39 @@ class Context:
         k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
         _check(lib().sdm_coalesce_step(self._ctx, float(dt), k, int(seed), int(step)),
                "sdm_coalesce_step")
+
+    def attach_transport(self, x, z, nx: int, nz: int, dx: float, dz: float):
+        """Positions (input order) on an nx x nz grid; re-sorts the storage by them."""
+        L = lib()
+        x_t = torch.as_tensor(x, dtype=torch.float64).to(self.device).contiguous()
+        z_t = torch.as_tensor(z, dtype=torch.float64).to(self.device).contiguous()
+        ws_bytes = int(L.sdm_transport_workspace_bytes(self.n_sd))
+        self.transport_workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8,
+                                               device=self.device)
+        base = self.transport_workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        torch.cuda.synchronize(self.device)
+        _check(L.sdm_transport_attach(self._ctx, aligned, ws_bytes + 256 - (aligned - base),
+                                      int(nx), int(nz), float(dx), float(dz), _dptr(x_t),
+                                      _dptr(z_t)), "sdm_transport_attach")
+
+    def transport(self, cx, cz, dt: float, sediment: bool = True):
+        """Advect by the Courant fields (device tensors or arrays, either None), sediment,
+        flag leavers, re-sort by cell."""
+        cx_t = None if cx is None else torch.as_tensor(cx, dtype=torch.float64).to(self.device).contiguous()
+        cz_t = None if cz is None else torch.as_tensor(cz, dtype=torch.float64).to(self.device).contiguous()
+        torch.cuda.synchronize(self.device)
+        _check(lib().sdm_transport_step(self._ctx, _dptr(cx_t), _dptr(cz_t), float(dt),
+                                        1 if sediment else 0), "sdm_transport_step")
+
+    def positions(self):
+        """(x, z) float64 tensors in input order."""
+        x = torch.empty(max(1, self.n_sd), dtype=torch.float64, device=self.device)
+        z = torch.empty(max(1, self.n_sd), dtype=torch.float64, device=self.device)
+        torch.cuda.synchronize(self.device)
+        _check(lib().sdm_transport_get_positions(self._ctx, _dptr(x), _dptr(z)),
+               "sdm_transport_get_positions")
+        return x[: self.n_sd], z[: self.n_sd]
 
     def set_rules(self, rules: int):
         """SDM rule flags (RULE_RELEASE | RULE_RECYCLE) for every later step."""
