@@ -12,7 +12,8 @@ dominant kernel (algorithmic bytes per launch / mean launch duration from HIP ev
 on the launch stream), and the FP64 CPU oracle timed on a bounded sample.
 
 Other workloads (--workload): domain2d, box, ensemble (batched vs per-instance plain
-launches), served (continuous batching vs sequential plain launches).
+launches), served (continuous batching vs sequential plain launches), transport
+(particle transport with a re-sort by cell, then coalescence, every step).
 """
 from __future__ import annotations
 
@@ -171,7 +172,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "domain2d", "box", "ensemble", "served"])
+                    choices=["large", "domain2d", "box", "ensemble", "served", "transport"])
     ap.add_argument("--nx", type=int, default=1024, help="cells per side (large domain)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")

@@ -248,9 +248,10 @@ sdm_status sdm_coalesce_adaptive(sdm_ctx *ctx, double dt, double p_limit, uint32
 /* ------------------------------------------------------------------------ */
 
 /* Bytes of the caller-owned device workspace sdm_transport_attach needs
- * (56 B per super-droplet: positions, their re-sort targets, and re-sort
- * targets of xi, r and the input index). */
-size_t sdm_transport_workspace_bytes(uint64_t n_sd);
+ * (about 72 B per super-droplet and 16 B per cell: positions, re-sort targets
+ * of positions, xi, r and the input index, and the re-sort of the particles
+ * that change cell). */
+size_t sdm_transport_workspace_bytes(uint64_t n_sd, uint32_t n_cells);
 
 /* Attach positions: x_in, z_in (dev double[n_sd], input order) inside
  * [0, nx dx) x [0, nz dz); nx * nz must equal n_cells.  From here on a
@@ -276,8 +277,9 @@ sdm_status sdm_transport_attach(sdm_ctx *ctx, void *workspace, size_t ws_bytes, 
  * z.  With sediment != 0 it then falls by v_t(r) dt (the kernel parameters'
  * terminal velocity, explicit Euler).  x wraps periodically; a particle whose z
  * leaves [0, nz dz) gets xi = 0 and is clamped into the boundary row.  The
- * storage is then re-sorted by cell (stable) and the plan rebuilt; pointers
- * from sdm_get_layout change.  Synchronises.  Errors: SDM_ESTATE (no transport
+ * storage is then re-sorted by cell, stable in the old storage order (only the
+ * particles that changed cell are sorted), and the plan rebuilt; pointers from
+ * sdm_get_layout change.  Synchronises.  Errors: SDM_ESTATE (no transport
  * attached), SDM_EINVAL (dt, or Courant numbers not finite or with
  * C_r - C_l >= 1 in some cell). */
 sdm_status sdm_transport_step(sdm_ctx *ctx, const double *cx, const double *cz, double dt,

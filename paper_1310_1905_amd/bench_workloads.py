@@ -6,6 +6,9 @@
               graph-replayed batch step vs per-instance plain launches
   served   -- Poisson request stream served by continuous batching vs one request at a
               time with plain launches; p50/p99 latency
+  transport -- the large domain (1024 x 1024 cells of 20 m) with particle transport:
+              single-eddy flow + sedimentation, re-sort by cell, then coalescence, every
+              step; or the 2D domain with --nx 75
 """
 from __future__ import annotations
 
@@ -136,6 +139,49 @@ def run_served(args):
                   "saturated_pair_tests_per_s": sum(r.pair_tests for r in res_sat) / sat_wall})
 
 
+def run_transport(args):
+    """Transport + coalescence per step; the two parts timed separately with HIP events."""
+    nx = args.nx
+    d = 20.0
+    pop = synth.large_domain(seed=synth.SEEDS[0], nx=nx, ny=nx) if nx > 75 else \
+        synth.domain_2d(seed=synth.SEEDS[0], nx=nx, ny=nx)
+    x, z = synth.positions_in_cells(pop, nx, nx, d, d, seed=5)
+    stream = torch.cuda.Stream()
+    ctx = sdm.Context(pop.cell, pop.xi, pop.r, pop.dV, stream=stream)
+    ctx.attach_transport(x, z, nx, nx, d, d)
+    cx, cz = synth.eddy_courant(nx, nx, d, d, pop.dt, w_max=2.0)
+    cx_t = torch.as_tensor(cx, device="cuda")
+    cz_t = torch.as_tensor(cz, device="cuda")
+    ctx.set_launch_config(group_slots=256, groups_per_wave=8, waves_per_block=1)
+    for t in range(args.warmup):
+        ctx.transport(cx_t, cz_t, pop.dt, sediment=True)
+        ctx.step(pop.dt, pop.kernel, pop.seed, t)
+    torch.cuda.synchronize()
+    p0, _ = ctx.stats()
+    tr = []
+    co = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        a = time.perf_counter()
+        ctx.transport(cx_t, cz_t, pop.dt, sediment=True)   # synchronises (re-plan)
+        b = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.step(pop.dt, pop.kernel, pop.seed, args.warmup + i)
+        e1.record(stream)
+        tr.append(b - a)
+        co.append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    p1, _ = ctx.stats()
+    co_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in co]))
+    return _line(args, (p1 - p0) / wall, wall * 1e3 / args.steps,
+                 f"transport_{nx}x{nx}_eddy_sedimentation_geometric",
+                 {"n_sd": pop.n_sd, "n_cells": pop.n_cells,
+                  "transport_ms_per_step": 1e3 * float(np.mean(tr)),
+                  "coalescence_ms_per_step": co_ms})
+
+
 def run(args):
     torch.cuda.set_device(0)
     if args.workload == "domain2d":
@@ -146,4 +192,6 @@ def run(args):
         return run_ensemble(args)
     if args.workload == "served":
         return run_served(args)
+    if args.workload == "transport":
+        return run_transport(args)
     raise ValueError(args.workload)

@@ -22,6 +22,16 @@ struct TransportState {
     double* r_alt = nullptr;
     uint32_t* id_alt = nullptr;
     uint32_t* cell = nullptr;   // new cell of every slot
+    // re-sort of the particles that changed cell
+    uint32_t* moved = nullptr;      // 1 if the slot's particle changed cell (n + 1 entries)
+    uint32_t* mprefix = nullptr;    // exclusive prefix of moved (n + 1)
+    uint32_t* mk = nullptr;         // movers: new cell, in old-slot order
+    uint32_t* mv = nullptr;         // movers: old slot
+    uint32_t* off_alt = nullptr;    // new slot offsets (swapped with the live offsets)
+    uint32_t* inc_off = nullptr;    // offsets of the incoming movers per new cell
+    uint32_t* in_low = nullptr;     // incoming movers from lower cells, per cell
+    uint32_t* count = nullptr;      // new slots per cell (n_cells + 1, last 0)
+    uint32_t* tile_sums = nullptr;  // scan scratch
 };
 
 }  // namespace sdm

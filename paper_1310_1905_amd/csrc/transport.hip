@@ -84,7 +84,7 @@ __global__ void k_transport(uint64_t n, uint32_t nx, uint32_t nz, double dx, dou
                             double dt, int sediment, KernelParams kp, double Lx, double Lz,
                             double* __restrict__ x, double* __restrict__ z,
                             uint64_t* __restrict__ xi, const double* __restrict__ r,
-                            uint32_t* __restrict__ cell)
+                            uint32_t* __restrict__ cell, uint32_t* __restrict__ moved)
 {
     for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
          s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
@@ -118,7 +118,118 @@ __global__ void k_transport(uint64_t n, uint32_t nx, uint32_t nz, double dx, dou
         }
         x[s] = xn;
         z[s] = zn;
-        cell[s] = column_of(xn, dx, nx) + nx * column_of(zn, dz, nz);
+        const uint32_t c_new = column_of(xn, dx, nx) + nx * column_of(zn, dz, nz);
+        cell[s] = c_new;
+        moved[s] = c_new != i + nx * k ? 1u : 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Re-sort after a transport step.  Only the particles that changed cell
+// ("movers") are sorted; the others keep their relative order.  In the stable
+// order by (new cell, old slot), cell c holds first the movers that come from
+// lower cells (old slot below c's old range), then its stayers, then the movers
+// from higher cells, each in old-slot order.  mprefix is the exclusive prefix
+// count of movers over the old slots.
+// ---------------------------------------------------------------------------
+__global__ void k_compact_movers(uint64_t n, const uint32_t* __restrict__ moved,
+                                 const uint32_t* __restrict__ mprefix,
+                                 const uint32_t* __restrict__ cell, uint32_t* __restrict__ mk,
+                                 uint32_t* __restrict__ mv)
+{
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        if (moved[s]) {
+            const uint32_t m = mprefix[s];
+            mk[m] = cell[s];
+            mv[m] = static_cast<uint32_t>(s);
+        }
+    }
+}
+
+// New per-cell counts (old - outgoing + incoming) and, per cell, the number of
+// incoming movers from lower cells.  count has n_cells + 1 entries (last 0).
+__global__ void k_new_counts(uint32_t n_cells, const uint32_t* __restrict__ old_off,
+                             const uint32_t* __restrict__ mprefix,
+                             const uint32_t* __restrict__ inc_off,
+                             const uint32_t* __restrict__ order, const uint32_t* __restrict__ mv,
+                             uint32_t* __restrict__ count, uint32_t* __restrict__ in_low)
+{
+    for (uint64_t c = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; c <= n_cells;
+         c += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        if (c == n_cells) {
+            count[c] = 0;
+            continue;
+        }
+        const uint32_t ob = old_off[c], oe = old_off[c + 1];
+        const uint32_t out = mprefix[oe] - mprefix[ob];
+        const uint32_t ib = inc_off[c], ie = inc_off[c + 1];
+        count[c] = (oe - ob) - out + (ie - ib);
+        // incoming movers are in old-slot order: count those below the cell's old range
+        uint32_t lo = ib, hi = ie;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (mv[order[mid]] < ob) lo = mid + 1;
+            else hi = mid;
+        }
+        in_low[c] = lo - ib;
+    }
+}
+
+// Stayers: destination from their rank among the cell's stayers.
+__global__ void k_scatter_stayers(uint64_t n, const uint32_t* __restrict__ moved,
+                                  const uint32_t* __restrict__ mprefix,
+                                  const uint32_t* __restrict__ cell,
+                                  const uint32_t* __restrict__ old_off,
+                                  const uint32_t* __restrict__ new_off,
+                                  const uint32_t* __restrict__ in_low,
+                                  const uint64_t* __restrict__ xi, const double* __restrict__ r,
+                                  const uint32_t* __restrict__ id, const double* __restrict__ x,
+                                  const double* __restrict__ z, uint64_t* __restrict__ xi_o,
+                                  double* __restrict__ r_o, uint32_t* __restrict__ id_o,
+                                  double* __restrict__ x_o, double* __restrict__ z_o)
+{
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        if (moved[s]) continue;
+        const uint32_t c = cell[s];
+        const uint32_t ob = old_off[c];
+        const uint64_t j = static_cast<uint64_t>(new_off[c]) + in_low[c] + (s - ob) -
+                           (mprefix[s] - mprefix[ob]);
+        xi_o[j] = xi[s];
+        r_o[j] = r[s];
+        id_o[j] = id[s];
+        x_o[j] = x[s];
+        z_o[j] = z[s];
+    }
+}
+
+// Movers, in the order sorted by (new cell, old slot).
+__global__ void k_scatter_movers(uint32_t m_tot, const uint32_t* __restrict__ order,
+                                 const uint32_t* __restrict__ mk, const uint32_t* __restrict__ mv,
+                                 const uint32_t* __restrict__ inc_off,
+                                 const uint32_t* __restrict__ new_off,
+                                 const uint32_t* __restrict__ in_low,
+                                 const uint32_t* __restrict__ count,
+                                 const uint64_t* __restrict__ xi, const double* __restrict__ r,
+                                 const uint32_t* __restrict__ id, const double* __restrict__ x,
+                                 const double* __restrict__ z, uint64_t* __restrict__ xi_o,
+                                 double* __restrict__ r_o, uint32_t* __restrict__ id_o,
+                                 double* __restrict__ x_o, double* __restrict__ z_o)
+{
+    for (uint64_t q = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; q < m_tot;
+         q += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint32_t e = order[q];
+        const uint32_t c = mk[e], s = mv[e];
+        const uint32_t rank = static_cast<uint32_t>(q) - inc_off[c];
+        const uint32_t in_c = inc_off[c + 1] - inc_off[c];
+        const uint32_t stayers = count[c] - in_c;
+        const uint64_t j = static_cast<uint64_t>(new_off[c]) + rank + (rank >= in_low[c] ? stayers : 0u);
+        xi_o[j] = xi[s];
+        r_o[j] = r[s];
+        id_o[j] = id[s];
+        x_o[j] = x[s];
+        z_o[j] = z[s];
     }
 }
 
@@ -153,11 +264,12 @@ __global__ void k_positions_out(uint64_t n, const uint32_t* id, const double* x,
 struct TransportLayout {
     double *x, *z, *x_alt, *z_alt, *r_alt;
     uint64_t* xi_alt;
-    uint32_t *id_alt, *cell;
+    uint32_t *id_alt, *cell, *moved, *mprefix, *mk, *mv;
+    uint32_t *off_alt, *inc_off, *in_low, *count, *tile_sums;
     size_t bytes;
 };
 
-TransportLayout transport_layout(void* ws, size_t ws_bytes, uint64_t n)
+TransportLayout transport_layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t nc)
 {
     Carver cv(ws, ws_bytes);
     TransportLayout L{};
@@ -169,6 +281,16 @@ TransportLayout transport_layout(void* ws, size_t ws_bytes, uint64_t n)
     L.r_alt = cv.take<double>(n);
     L.id_alt = cv.take<uint32_t>(n);
     L.cell = cv.take<uint32_t>(n);
+    L.moved = cv.take<uint32_t>(n + 1);
+    L.mprefix = cv.take<uint32_t>(n + 1);
+    L.mk = cv.take<uint32_t>(n);
+    L.mv = cv.take<uint32_t>(n);
+    L.off_alt = cv.take<uint32_t>(uint64_t(nc) + 1);
+    L.inc_off = cv.take<uint32_t>(uint64_t(nc) + 1);
+    L.in_low = cv.take<uint32_t>(nc);
+    L.count = cv.take<uint32_t>(uint64_t(nc) + 1);
+    const uint64_t longest = (n + 1) > (uint64_t(nc) + 1) ? (n + 1) : (uint64_t(nc) + 1);
+    L.tile_sums = cv.take<uint32_t>((longest + kScanTile - 1) / kScanTile + 2);
     L.bytes = cv.used();
     return L;
 }
@@ -188,7 +310,19 @@ sdm_status clear_error(sdm_ctx* x)
     return SDM_OK;
 }
 
-// Stable re-sort of the storage by T.cell, then a new launch plan.
+void swap_state(sdm_ctx* x)
+{
+    TransportState& T = *x->transport;
+    std::swap(x->xi, T.xi_alt);
+    std::swap(x->r, T.r_alt);
+    std::swap(x->id, T.id_alt);
+    std::swap(T.x, T.x_alt);
+    std::swap(T.z, T.z_alt);
+}
+
+sdm_status refresh_plan(sdm_ctx* x);
+
+// Stable re-sort of the whole storage by T.cell, then a new launch plan.
 sdm_status resort(sdm_ctx* x)
 {
     TransportState& T = *x->transport;
@@ -200,12 +334,48 @@ sdm_status resort(sdm_ctx* x)
                            order, x->xi, x->r, x->id, T.x, T.z, T.xi_alt, T.r_alt, T.id_alt,
                            T.x_alt, T.z_alt);
         SDM_LAUNCHED();
-        std::swap(x->xi, T.xi_alt);
-        std::swap(x->r, T.r_alt);
-        std::swap(x->id, T.id_alt);
-        std::swap(T.x, T.x_alt);
-        std::swap(T.z, T.z_alt);
+        swap_state(x);
     }
+    return refresh_plan(x);
+}
+
+// The same order after a transport step, sorting only the movers.
+sdm_status resort_moved(sdm_ctx* x)
+{
+    TransportState& T = *x->transport;
+    const uint64_t n = x->n_sd;
+    const uint32_t nc = x->n_cells;
+    hipStream_t st = x->stream;
+    SDM_TRY(scan_exclusive(st, T.moved, T.mprefix, n + 1, T.tile_sums));
+    uint32_t m_tot = 0;
+    SDM_HIP(hipMemcpyAsync(&m_tot, T.mprefix + n, sizeof(m_tot), hipMemcpyDeviceToHost, st));
+    SDM_HIP(hipStreamSynchronize(st));
+    if (m_tot == 0) return SDM_OK;   // nobody changed cell: storage, offsets and plan stay
+    hipLaunchKernelGGL(k_compact_movers, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, T.moved,
+                       T.mprefix, T.cell, T.mk, T.mv);
+    SDM_LAUNCHED();
+    const uint32_t* order = nullptr;
+    SDM_TRY(radix_sort_by_cell(st, m_tot, T.mk, nc, x->sort, T.inc_off, &order));
+    hipLaunchKernelGGL(k_new_counts, dim3(grid_for(uint64_t(nc) + 1, 256, 8192)), dim3(256), 0, st,
+                       nc, x->offsets, T.mprefix, T.inc_off, order, T.mv, T.count, T.in_low);
+    SDM_LAUNCHED();
+    SDM_TRY(scan_exclusive(st, T.count, T.off_alt, uint64_t(nc) + 1, T.tile_sums));
+    hipLaunchKernelGGL(k_scatter_stayers, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n,
+                       T.moved, T.mprefix, T.cell, x->offsets, T.off_alt, T.in_low, x->xi, x->r,
+                       x->id, T.x, T.z, T.xi_alt, T.r_alt, T.id_alt, T.x_alt, T.z_alt);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL(k_scatter_movers, dim3(grid_for(m_tot, 256, 8192)), dim3(256), 0, st, m_tot,
+                       order, T.mk, T.mv, T.inc_off, T.off_alt, T.in_low, T.count, x->xi, x->r,
+                       x->id, T.x, T.z, T.xi_alt, T.r_alt, T.id_alt, T.x_alt, T.z_alt);
+    SDM_LAUNCHED();
+    swap_state(x);
+    std::swap(x->offsets, T.off_alt);
+    return refresh_plan(x);
+}
+
+// Launch plan from the new offsets.
+sdm_status refresh_plan(sdm_ctx* x)
+{
     std::vector<uint32_t> off(uint64_t(x->n_cells) + 1);
     SDM_HIP(hipMemcpyAsync(off.data(), x->offsets, off.size() * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, x->stream));
@@ -229,9 +399,9 @@ sdm_status check_attached(const sdm_ctx* x)
 
 }  // namespace
 
-extern "C" size_t sdm_transport_workspace_bytes(uint64_t n_sd)
+extern "C" size_t sdm_transport_workspace_bytes(uint64_t n_sd, uint32_t n_cells)
 {
-    return transport_layout(nullptr, 0, n_sd).bytes;
+    return transport_layout(nullptr, 0, n_sd, n_cells).bytes;
 }
 
 extern "C" sdm_status sdm_transport_attach(sdm_ctx* x, void* workspace, size_t ws_bytes,
@@ -262,7 +432,7 @@ extern "C" sdm_status sdm_transport_attach(sdm_ctx* x, void* workspace, size_t w
         set_error("workspace must be non-NULL and 256-byte aligned");
         return SDM_EINVAL;
     }
-    const TransportLayout L = transport_layout(workspace, ws_bytes, x->n_sd);
+    const TransportLayout L = transport_layout(workspace, ws_bytes, x->n_sd, x->n_cells);
     if (L.bytes > ws_bytes) {
         set_error("transport workspace has %zu bytes, %zu needed", ws_bytes, L.bytes);
         return SDM_ENOMEM;
@@ -294,7 +464,20 @@ extern "C" sdm_status sdm_transport_attach(sdm_ctx* x, void* workspace, size_t w
     T->r_alt = L.r_alt;
     T->id_alt = L.id_alt;
     T->cell = L.cell;
+    T->moved = L.moved;
+    T->mprefix = L.mprefix;
+    T->mk = L.mk;
+    T->mv = L.mv;
+    T->off_alt = L.off_alt;
+    T->inc_off = L.inc_off;
+    T->in_low = L.in_low;
+    T->count = L.count;
+    T->tile_sums = L.tile_sums;
     x->transport = std::move(T);
+    // the flag past the last slot stays 0, so the prefix over n + 1 flags ends in the total
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n + 1, 256, 8192)), dim3(256), 0, x->stream,
+                       L.moved, n + 1, 0u);
+    SDM_LAUNCHED();
     if (n > 0) {
         hipLaunchKernelGGL(k_cells_of, dim3(grid_for(n, 256, 8192)), dim3(256), 0, x->stream, n,
                            L.x, L.z, nx, nz, dx, dz, L.cell);
@@ -329,10 +512,10 @@ extern "C" sdm_status sdm_transport_step(sdm_ctx* x, const double* cx, const dou
         hipLaunchKernelGGL(k_transport, dim3(grid_for(n, 256, 8192)), dim3(256), 0, x->stream, n,
                            T.nx, T.nz, T.dx, T.dz, cx, cz, dt, sediment ? 1 : 0, to_kp(x->params),
                            static_cast<double>(T.nx) * T.dx, static_cast<double>(T.nz) * T.dz,
-                           T.x, T.z, x->xi, x->r, T.cell);
+                           T.x, T.z, x->xi, x->r, T.cell, T.moved);
         SDM_LAUNCHED();
     }
-    return resort(x);
+    return resort_moved(x);
 }
 
 extern "C" sdm_status sdm_transport_get_positions(sdm_ctx* x, double* x_out, double* z_out)

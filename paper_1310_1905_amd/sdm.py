@@ -80,7 +80,7 @@ def lib() -> ctypes.CDLL:
         "sdm_get_rules": (ctypes.c_int, [_P, _P]),
         "sdm_recycle": (ctypes.c_int, [_P]),
         "sdm_get_recycled": (ctypes.c_int, [_P, _P]),
-        "sdm_transport_workspace_bytes": (_sz, [_u64]),
+        "sdm_transport_workspace_bytes": (_sz, [_u64, _u32]),
         "sdm_transport_attach": (ctypes.c_int, [_P, _P, _sz, _u32, _u32, _dbl, _dbl, _P, _P]),
         "sdm_transport_step": (ctypes.c_int, [_P, _P, _P, _dbl, ctypes.c_int]),
         "sdm_transport_get_positions": (ctypes.c_int, [_P, _P, _P]),
@@ -197,7 +197,7 @@ class Context:
         L = lib()
         x_t = torch.as_tensor(x, dtype=torch.float64).to(self.device).contiguous()
         z_t = torch.as_tensor(z, dtype=torch.float64).to(self.device).contiguous()
-        ws_bytes = int(L.sdm_transport_workspace_bytes(self.n_sd))
+        ws_bytes = int(L.sdm_transport_workspace_bytes(self.n_sd, self.n_cells))
         self.transport_workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8,
                                                device=self.device)
         base = self.transport_workspace.data_ptr()
