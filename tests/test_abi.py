@@ -65,3 +65,34 @@ def test_error_paths_before_device_work(L):
                       None) == -1
     assert out.value is None
     assert L.sdm_batch_create(ctypes.byref(out), None, 256, 1 << 20, 100, 0, 1) == -1
+
+
+def test_null_context_rejected_by_every_context_call(L):
+    """Every entry point that takes a context reports SDM_EINVAL for NULL, on the host."""
+    calls = [
+        lambda: L.sdm_get_state(None, None, None),
+        lambda: L.sdm_get_stats(None, None, None),
+        lambda: L.sdm_debug_permutation(None, 0, 0, None, None),
+        lambda: L.sdm_set_rules(None, 0),
+        lambda: L.sdm_get_rules(None, None),
+        lambda: L.sdm_recycle(None),
+        lambda: L.sdm_get_recycled(None, None),
+        lambda: L.sdm_diag_sd_conc(None, None),
+        lambda: L.sdm_diag_moments(None, 0, 0.0, 1.0, None, None),
+        lambda: L.sdm_probe_probability(None, 1.0, 0, 0, 0, None, None),
+        lambda: L.sdm_coalesce_substeps(None, 1.0, 1, 0, 0, 0),
+        lambda: L.sdm_coalesce_adaptive(None, 1.0, 0.5, 4, 0, 0, 0, None),
+        lambda: L.sdm_transport_attach(None, None, 0, 1, 1, 1.0, 1.0, None, None),
+        lambda: L.sdm_transport_step(None, None, None, 1.0, 0),
+        lambda: L.sdm_transport_get_positions(None, None, None),
+    ]
+    for call in calls:
+        assert call() == -1
+        assert b"NULL" in L.sdm_last_error()
+
+
+def test_transport_workspace_grows_with_size(L):
+    a = L.sdm_transport_workspace_bytes(1000, 16)
+    b = L.sdm_transport_workspace_bytes(2000, 16)
+    c = L.sdm_transport_workspace_bytes(2000, 4096)
+    assert 56 * 1000 < a < b < c
