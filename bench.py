@@ -172,7 +172,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "domain2d", "box", "ensemble", "served", "transport"])
+                    choices=["large", "domain2d", "box", "ensemble", "served", "transport",
+                             "extras"])
     ap.add_argument("--nx", type=int, default=1024, help="cells per side (large domain)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")

@@ -6,6 +6,8 @@
               graph-replayed batch step vs per-instance plain launches
   served   -- Poisson request stream served by continuous batching vs one request at a
               time with plain launches; p50/p99 latency
+  extras   -- the large domain: step time under the release rules with recycling, and the
+              per-cell moment, concentration and P_ij-probe kernels (HIP events)
   transport -- the large domain (1024 x 1024 cells of 20 m) with particle transport:
               single-eddy flow + sedimentation, re-sort by cell, then coalescence, every
               step; or the 2D domain with --nx 75
@@ -182,6 +184,60 @@ def run_transport(args):
                   "coalescence_ms_per_step": co_ms})
 
 
+def _timed(stream, fn, reps):
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+
+
+def run_extras(args):
+    """Costs of the rows beyond the plain step, on the large domain."""
+    pop = synth.large_domain(seed=synth.SEEDS[0], nx=args.nx, ny=args.nx)
+    stream = torch.cuda.Stream()
+    ctx = sdm.Context(pop.cell, pop.xi, pop.r, pop.dV, stream=stream)
+    ctx.set_launch_config(group_slots=256, groups_per_wave=8, waves_per_block=1)
+    reps = max(3, args.steps)
+    step = [0]
+
+    def one_step():
+        ctx.step(pop.dt, pop.kernel, pop.seed, step[0])
+        step[0] += 1
+
+    for _ in range(args.warmup):
+        one_step()
+    plain_ms = _timed(stream, one_step, reps)
+    ctx.set_rules(sdm.RULE_RELEASE | sdm.RULE_RECYCLE)
+    for _ in range(args.warmup):
+        one_step()
+    rules_ms = _timed(stream, one_step, reps)
+    recycled = ctx.recycled()
+    ctx.set_rules(0)
+    n_sd, n_cells = pop.n_sd, pop.n_cells
+    out_m = torch.empty(n_cells, dtype=torch.float64, device="cuda")
+    out_c = torch.empty(n_cells, dtype=torch.int32, device="cuda")
+    L = sdm.lib()
+    torch.cuda.synchronize()
+    mom_ms = _timed(stream, lambda: L.sdm_diag_moments(ctx._ctx, 3, 0.0, float("inf"), None,
+                                                      out_m.data_ptr()), reps)
+    conc_ms = _timed(stream, lambda: L.sdm_diag_sd_conc(ctx._ctx, out_c.data_ptr()), reps)
+    probe_ms = _timed(stream, lambda: L.sdm_probe_probability(ctx._ctx, pop.dt, 1, pop.seed, 0,
+                                                             None, None), reps)
+    mom_bytes = 16 * n_sd + 12 * n_cells + 8 * n_cells
+    conc_bytes = 8 * n_sd + 4 * n_cells + 4 * n_cells
+    return _line(args, n_sd / (mom_ms * 1e-3), plain_ms, "extras_large_domain_1024x1024",
+                 {"n_sd": n_sd, "n_cells": n_cells, "plain_step_ms": plain_ms,
+                  "release_rules_recycling_step_ms": rules_ms, "recycled_slots": recycled,
+                  "moments_ms": mom_ms, "moments_GBps": mom_bytes / (mom_ms * 1e-3) / 1e9,
+                  "sd_conc_ms": conc_ms, "sd_conc_GBps": conc_bytes / (conc_ms * 1e-3) / 1e9,
+                  "probe_ms": probe_ms},
+                 unit="SDs/s (moment kernel)")
+
+
 def run(args):
     torch.cuda.set_device(0)
     if args.workload == "domain2d":
@@ -194,4 +250,6 @@ def run(args):
         return run_served(args)
     if args.workload == "transport":
         return run_transport(args)
+    if args.workload == "extras":
+        return run_extras(args)
     raise ValueError(args.workload)

@@ -309,9 +309,17 @@ static uint32_t substep_count(double pmax, double p_limit, uint32_t max_substeps
     return q >= static_cast<double>(max_substeps) ? max_substeps : static_cast<uint32_t>(q);
 }
 
+// One wavefront per cell, as many as there are cells (up to 2^20 workgroups),
+// so that every cell's loads are in flight at once.
 static uint32_t diag_grid(uint32_t n_cells)
 {
-    return grid_for(n_cells, kDiagCellsPerBlock, 1u << 16);
+    return grid_for(n_cells, kDiagCellsPerBlock, 1u << 20);
+}
+
+// The probe ends in one global atomic per workgroup: fewer, longer-lived workgroups.
+static uint32_t probe_grid(uint32_t n_cells)
+{
+    return grid_for(n_cells, kDiagCellsPerBlock, 1u << 14);
 }
 
 extern "C" sdm_status sdm_diag_sd_conc(sdm_ctx* x, uint32_t* out)
@@ -367,7 +375,7 @@ static sdm_status enqueue_probe(sdm_ctx* x, double dt, sdm_kernel kernel, uint64
     a.perm_out = x->probe_order;
     a.nlive_out = x->probe_nlive;
     SDM_TRY(launch(x, a, true));
-    hipLaunchKernelGGL(k_probe_pairs, dim3(diag_grid(x->n_cells)), dim3(kDiagBlock), 0, x->stream,
+    hipLaunchKernelGGL(k_probe_pairs, dim3(probe_grid(x->n_cells)), dim3(kDiagBlock), 0, x->stream,
                        x->offsets, x->dV, x->xi, x->r, x->probe_order, x->probe_nlive, x->n_cells,
                        static_cast<uint32_t>(kernel), a.kp, dt, cell_max, x->probe_max);
     SDM_LAUNCHED();

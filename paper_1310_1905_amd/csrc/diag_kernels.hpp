@@ -54,13 +54,23 @@ __global__ __launch_bounds__(kDiagBlock) void k_moments(const uint32_t* __restri
          c < n_cells; c += stride) {
         const uint32_t b = off[c], n = off[c + 1] - b;
         double acc = 0.0;
-        for (uint32_t i = lane; i < n; i += 64u) {
-            const uint64_t x = xi[b + i];
-            const double ri = r[b + i];
-            if (x != 0 && ri >= r_min && ri <= r_max) {
-                double rk = 1.0;
-                for (uint32_t e = 0; e < k; ++e) rk = rk * ri;
-                acc = acc + static_cast<double>(x) * rk;
+        // slots lane, lane + 64, ... in ascending order; four rows of loads in flight
+        for (uint32_t base = 0; base < n; base += 4u * 64u) {
+            uint64_t xv[4];
+            double rv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t i = base + lane + 64u * t;
+                xv[t] = i < n ? xi[b + i] : 0u;
+                rv[t] = i < n ? r[b + i] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (xv[t] != 0 && rv[t] >= r_min && rv[t] <= r_max) {
+                    double rk = 1.0;
+                    for (uint32_t e = 0; e < k; ++e) rk = rk * rv[t];
+                    acc = acc + static_cast<double>(xv[t]) * rk;
+                }
             }
         }
         acc = wave_fold_sum(acc, lane);
@@ -79,9 +89,15 @@ __global__ __launch_bounds__(kDiagBlock) void k_sd_conc(const uint32_t* __restri
          c < n_cells; c += stride) {
         const uint32_t b = off[c], n = off[c + 1] - b;
         uint32_t cnt = 0;
-        for (uint32_t base = 0; base < n; base += 64u) {
-            const bool live = base + lane < n && xi[b + base + lane] != 0;
-            cnt += static_cast<uint32_t>(__popcll(__ballot(live)));
+        for (uint32_t base = 0; base < n; base += 4u * 64u) {
+            uint64_t xv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t i = base + lane + 64u * t;
+                xv[t] = i < n ? xi[b + i] : 0u;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) cnt += static_cast<uint32_t>(__popcll(__ballot(xv[t] != 0)));
         }
         if (lane == 0) out[c] = cnt;
     }
@@ -119,8 +135,15 @@ __global__ __launch_bounds__(kDiagBlock) void k_probe_pairs(
         if (lane == 0 && cell_max) cell_max[c] = best;
         wave_best = fmax(wave_best, best);
     }
-    if (lane == 0 && wave_best > 0.0)
-        atomicMax(gmax, static_cast<unsigned long long>(__double_as_longlong(wave_best)));
+    // one atomic per workgroup (a single counter word takes every update in turn)
+    __shared__ double s_best[kDiagCellsPerBlock];
+    if (lane == 0) s_best[threadIdx.x / 64u] = wave_best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = s_best[0];
+        for (uint32_t w = 1; w < kDiagCellsPerBlock; ++w) b = fmax(b, s_best[w]);
+        if (b > 0.0) atomicMax(gmax, static_cast<unsigned long long>(__double_as_longlong(b)));
+    }
 }
 
 }  // namespace

@@ -10,8 +10,10 @@
 // and keeps xi_d - floor(xi_d / 2).
 //
 // One wavefront per cell.  The threshold T (the take-th largest multiplicity)
-// is found bit by bit from the top as the largest v with #{xi >= v} >= take;
-// the donors are then every slot above T plus the lowest-slot ones equal to T.
+// is the largest multiplicity when take = 1, else found bit by bit from the top
+// as the largest v with #{xi >= v} >= take (the first 256 slots of the cell are
+// counted from registers with ballots, any further ones from memory); the
+// donors are then every slot above T plus the lowest-slot ones equal to T.
 // Dead and donor slots are listed in slot order (ballot prefix counts) in a
 // per-cell scratch range, and the list pairs are applied last, so no slot is
 // classified after it has been written.
@@ -24,6 +26,7 @@ namespace {
 
 constexpr int kRecycleBlock = 256;
 constexpr uint32_t kRecycleCellsPerBlock = kRecycleBlock / 64;
+constexpr int kRecycleRegs = 4;   // slots per lane held in registers (256 per cell)
 
 __device__ __forceinline__ uint32_t wave_total(uint32_t v)
 {
@@ -42,13 +45,22 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
     return v;
 }
 
-// Live slots of [b, b+n) whose multiplicity is >= v (v >= 1).
+// Slots of [b, b+n) whose multiplicity is >= v (v >= 1): the first
+// 64 * kRecycleRegs from the registers xr, the rest from memory.
 __device__ __forceinline__ uint32_t count_at_least(const uint64_t* __restrict__ xi, uint32_t b,
-                                                   uint32_t n, uint64_t v, uint32_t lane)
+                                                   uint32_t n, const uint64_t (&xr)[kRecycleRegs],
+                                                   uint64_t v, uint32_t lane)
 {
     uint32_t c = 0;
-    for (uint32_t i = lane; i < n; i += 64u) c += xi[b + i] >= v ? 1u : 0u;
-    return wave_total(c);
+#pragma unroll
+    for (int k = 0; k < kRecycleRegs; ++k)
+        c += static_cast<uint32_t>(__popcll(__ballot(xr[k] >= v)));
+    if (n > 64u * kRecycleRegs) {
+        uint32_t t = 0;
+        for (uint32_t i = 64u * kRecycleRegs + lane; i < n; i += 64u) t += xi[b + i] >= v ? 1u : 0u;
+        c += wave_total(t);
+    }
+    return c;
 }
 
 // list: uint32[n_sd] scratch, cell c uses [off[c], off[c+1]).
@@ -67,10 +79,24 @@ __global__ __launch_bounds__(kRecycleBlock) void k_recycle(const uint32_t* __res
     for (uint64_t c = static_cast<uint64_t>(blockIdx.x) * kRecycleCellsPerBlock + threadIdx.x / 64u;
          c < n_cells; c += stride) {
         const uint32_t b = off[c], n = off[c + 1] - b;
-        // counts of dead and live slots, largest multiplicity
+        // the first 256 slots into registers (independent loads), then the counts of
+        // dead and live slots and the largest multiplicity
+        uint64_t xr[kRecycleRegs];
+#pragma unroll
+        for (int k = 0; k < kRecycleRegs; ++k) {
+            const uint32_t i = lane + 64u * k;
+            xr[k] = i < n ? xi[b + i] : 0u;
+        }
         uint32_t z = 0, L = 0;
         uint64_t xmax = 0;
-        for (uint32_t base = 0; base < n; base += 64u) {
+#pragma unroll
+        for (int k = 0; k < kRecycleRegs; ++k) {
+            const uint32_t i = lane + 64u * k;
+            z += static_cast<uint32_t>(__popcll(__ballot(i < n && xr[k] == 0)));
+            L += static_cast<uint32_t>(__popcll(__ballot(xr[k] != 0)));
+            xmax = xr[k] > xmax ? xr[k] : xmax;
+        }
+        for (uint32_t base = 64u * kRecycleRegs; base < n; base += 64u) {
             const uint32_t i = base + lane;
             const uint64_t x = i < n ? xi[b + i] : 0u;
             z += static_cast<uint32_t>(__popcll(__ballot(i < n && x == 0)));
@@ -81,12 +107,15 @@ __global__ __launch_bounds__(kRecycleBlock) void k_recycle(const uint32_t* __res
         xmax = wave_max_u64(xmax);
         const uint32_t take = z < L ? z : L;
         // threshold: the take-th largest multiplicity
-        uint64_t T = 0;
-        for (int bit = 63 - __clzll(static_cast<long long>(xmax)); bit >= 0; --bit) {
-            const uint64_t cand = T | (1ull << bit);
-            if (count_at_least(xi, b, n, cand, lane) >= take) T = cand;
+        uint64_t T = xmax;
+        if (take > 1) {
+            T = 0;
+            for (int bit = 63 - __clzll(static_cast<long long>(xmax)); bit >= 0; --bit) {
+                const uint64_t cand = T | (1ull << bit);
+                if (count_at_least(xi, b, n, xr, cand, lane) >= take) T = cand;
+            }
         }
-        const uint32_t above = count_at_least(xi, b, n, T + 1u, lane);
+        const uint32_t above = count_at_least(xi, b, n, xr, T + 1u, lane);
         const uint32_t need_eq = take - above;
         // dead slots to list[b, b+z), split donors to list[b+z, b+z+nd), slot order
         uint32_t dead_seen = 0, eq_seen = 0, don_seen = 0;
@@ -120,7 +149,15 @@ __global__ __launch_bounds__(kRecycleBlock) void k_recycle(const uint32_t* __res
         }
         done += nd;
     }
-    if (recycled && lane == 0 && done) atomicAdd(recycled, static_cast<unsigned long long>(done));
+    // one atomic per workgroup
+    __shared__ uint32_t s_done[kRecycleCellsPerBlock];
+    if (lane == 0) s_done[threadIdx.x / 64u] = done;
+    __syncthreads();
+    if (threadIdx.x == 0 && recycled) {
+        uint32_t t = 0;
+        for (uint32_t w = 0; w < kRecycleCellsPerBlock; ++w) t += s_done[w];
+        if (t) atomicAdd(recycled, static_cast<unsigned long long>(t));
+    }
 }
 
 }  // namespace
