@@ -189,9 +189,9 @@ def main():
                          "block_threads,xcd_remap (skips the autotuner)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the coalescence step "
-                                   "shards by cells with no exchange (see DESIGN.md), but no "
-                                   "multi-GPU path is provided", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "only one GPU is supported: the coalescence step would "
+                                   "shard by cell ranges with no exchange, but no multi-GPU "
+                                   "path is provided", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "large":
         out = bench_large(args)
