@@ -191,16 +191,20 @@ __global__ void k_scatter_stayers(uint64_t n, const uint32_t* __restrict__ moved
 {
     for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
          s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        if (moved[s]) continue;
-        const uint32_t c = cell[s];
+        // the slot's own loads first, all independent; the cell's offsets after
+        const uint32_t mv_s = moved[s], c = cell[s], mp = mprefix[s];
+        const uint64_t xv = xi[s];
+        const double rv = r[s], xs = x[s], zs = z[s];
+        const uint32_t iv = id[s];
+        if (mv_s) continue;
         const uint32_t ob = old_off[c];
         const uint64_t j = static_cast<uint64_t>(new_off[c]) + in_low[c] + (s - ob) -
-                           (mprefix[s] - mprefix[ob]);
-        xi_o[j] = xi[s];
-        r_o[j] = r[s];
-        id_o[j] = id[s];
-        x_o[j] = x[s];
-        z_o[j] = z[s];
+                           (mp - mprefix[ob]);
+        xi_o[j] = xv;
+        r_o[j] = rv;
+        id_o[j] = iv;
+        x_o[j] = xs;
+        z_o[j] = zs;
     }
 }
 
@@ -221,15 +225,18 @@ __global__ void k_scatter_movers(uint32_t m_tot, const uint32_t* __restrict__ or
          q += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
         const uint32_t e = order[q];
         const uint32_t c = mk[e], s = mv[e];
+        const uint64_t xv = xi[s];
+        const double rv = r[s], xs = x[s], zs = z[s];
+        const uint32_t iv = id[s];
         const uint32_t rank = static_cast<uint32_t>(q) - inc_off[c];
         const uint32_t in_c = inc_off[c + 1] - inc_off[c];
         const uint32_t stayers = count[c] - in_c;
         const uint64_t j = static_cast<uint64_t>(new_off[c]) + rank + (rank >= in_low[c] ? stayers : 0u);
-        xi_o[j] = xi[s];
-        r_o[j] = r[s];
-        id_o[j] = id[s];
-        x_o[j] = x[s];
-        z_o[j] = z[s];
+        xi_o[j] = xv;
+        r_o[j] = rv;
+        id_o[j] = iv;
+        x_o[j] = xs;
+        z_o[j] = zs;
     }
 }
 
