@@ -102,7 +102,8 @@ sdm_status check_ctx(const sdm_ctx* x)
 sdm_status upload_plan(sdm_ctx* x)
 {
     Plan plan;
-    plan_cells(plan, 0, x->sizes.data(), x->n_cells, x->shape.group_slots);
+    plan_cells(plan, 0, x->sizes.data(), x->n_cells, x->shape.group_slots,
+               grid_threshold(x->sizes.data(), x->n_cells, x->shape.group_slots));
     plan_finish(plan);
     const size_t ng = plan.group_begin.size();
     if (ng) {

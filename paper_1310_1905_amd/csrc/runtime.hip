@@ -130,7 +130,7 @@ sdm_status radix_sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, u
 
 // ------------------------------------------------------------ step plan
 void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_cells,
-                uint32_t group_slots)
+                uint32_t group_slots, uint32_t grid_min)
 {
     uint32_t g_start = 0, g_slots = 0;
     bool open = false;
@@ -143,7 +143,7 @@ void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_
                 plan.group_end.push_back(c);
                 open = false;
             }
-            if (n > kGridMinSlots) {
+            if (n > grid_min) {
                 plan.grid.push_back(GridCell{c, 0, 0, 0, 0, 0, 0, 0});
                 plan.grid_sizes.push_back(n);
             } else {
@@ -169,6 +169,13 @@ void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_
         plan.group_begin.push_back(g_start);
         plan.group_end.push_back(c_begin + n_cells);
     }
+}
+
+uint32_t grid_threshold(const uint32_t* sizes, uint32_t n_cells, uint32_t group_slots)
+{
+    uint32_t big = 0;
+    for (uint32_t i = 0; i < n_cells && big < kFewBigCells; ++i) big += sizes[i] > group_slots;
+    return big < kFewBigCells ? kGridMinSlotsFew : kGridMinSlots;
 }
 
 void plan_finish(Plan& plan)
@@ -214,7 +221,7 @@ bool shape_valid(const LaunchShape& c)
 
 void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g)
 {
-    g->cap_cells = n_sd / (kGridMinSlots + 1) + 1;
+    g->cap_cells = n_sd / (kGridMinSlotsFew + 1) + 1;
     g->cap_chunks = n_sd / kGridChunk + g->cap_cells;
     g->cap_tiles = n_sd / 2 / kGridTile + g->cap_cells;
     g->cap_pchunks = n_sd / 2 / kGridPairChunk + g->cap_cells;

@@ -155,7 +155,10 @@ void grid_args(const GridArrays& g, StepArgs* a);
 // are packed greedily into groups of at most group_slots slots and
 // kGroupMaxCells cells.
 void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_cells,
-                uint32_t group_slots);
+                uint32_t group_slots, uint32_t grid_min);
+// Size above which a cell goes to the grid tier: kGridMinSlotsFew when fewer than
+// kFewBigCells cells exceed group_slots, else kGridMinSlots.
+uint32_t grid_threshold(const uint32_t* sizes, uint32_t n_cells, uint32_t group_slots);
 void plan_finish(Plan& plan);
 
 // Enqueue the wave-tier, workgroup-tier and grid-tier kernels for one step

@@ -844,13 +844,18 @@ __global__ __launch_bounds__(BLOCK) void k_block_cells(const StepArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Grid tier: cells above kGridMinSlots storage slots, each spread over many
+// Grid tier: cells above kGridMinSlots storage slots (kGridMinSlotsFew when a
+// context has fewer than kFewBigCells cells beyond the wave tier), each spread over many
 // workgroups.  The step is a sequence of launches over all grid cells at once:
 // zero the bucket counters -> keys and bucket counts (global atomics) -> tile
 // sums -> per-cell scan of tile sums -> tile scans -> scatter -> in-bucket rank
 // -> pair tests.  Same algorithm and results as the other tiers.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kGridMinSlots = 16384;
+// With few cells above the wave-tier capacity, one workgroup per cell leaves most
+// of the chip idle; such contexts send cells from this size on to the grid tier.
+constexpr uint32_t kGridMinSlotsFew = 4096;
+constexpr uint32_t kFewBigCells = 256;
 constexpr int kGridBlock = 256;
 constexpr uint32_t kGridChunk = 2048;     // slots per slot chunk (multiple of 4)
 constexpr uint32_t kGridTile = 4096;      // buckets per bucket tile
