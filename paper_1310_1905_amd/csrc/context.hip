@@ -101,6 +101,15 @@ sdm_status check_ctx(const sdm_ctx* x)
 // Build the work lists for the current launch shape and upload them.
 sdm_status upload_plan(sdm_ctx* x)
 {
+    if (x->sizes_stale) {
+        // the storage was re-sorted on the device since the host last saw the offsets
+        std::vector<uint32_t> off(uint64_t(x->n_cells) + 1);
+        SDM_HIP(hipMemcpyAsync(off.data(), x->offsets, off.size() * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, x->stream));
+        SDM_HIP(hipStreamSynchronize(x->stream));
+        for (uint32_t c = 0; c < x->n_cells; ++c) x->sizes[c] = off[c + 1] - off[c];
+        x->sizes_stale = false;
+    }
     Plan plan;
     plan_cells(plan, 0, x->sizes.data(), x->n_cells, x->shape.group_slots,
                grid_threshold(x->sizes.data(), x->n_cells, x->shape.group_slots));

@@ -32,6 +32,12 @@ struct TransportState {
     uint32_t* in_low = nullptr;     // incoming movers from lower cells, per cell
     uint32_t* count = nullptr;      // new slots per cell (n_cells + 1, last 0)
     uint32_t* tile_sums = nullptr;  // scan scratch
+    // launch plan on the device
+    uint8_t* jump = nullptr;        // cells of the greedy group a cell would open
+    uint8_t* exits = nullptr;       // chunk walk exits per entry
+    uint8_t* entries = nullptr;     // chunk walk entries
+    uint32_t* start = nullptr;      // group-start flags, then their prefix
+    uint32_t* plan_info = nullptr;  // [0] large-cell flag, [1] plan check flag
 };
 
 }  // namespace sdm
@@ -62,6 +68,7 @@ struct sdm_ctx {
     uint32_t* scr_cnt = nullptr;
     // plan
     std::vector<uint32_t> sizes;   // storage slots per cell (host copy)
+    bool sizes_stale = false;      // sizes behind the device offsets (device-planned)
     uint32_t n_groups = 0, n_wave_cells = 0, n_block = 0;
     sdm::LaunchShape shape;
     uint32_t rules = 0;   // sdm_rule flags applied by every step

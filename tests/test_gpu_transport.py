@@ -118,6 +118,30 @@ def test_domain_2d_all_processes(sdm_mod, oracle_mod):
     assert ref.stats[1] > 0
 
 
+@pytest.mark.parametrize("slots", [256, 512])
+def test_device_plan_equals_host_plan(sdm_mod, oracle_mod, slots):
+    """After a transport step the launch plan is built on the device; it must match
+    the host's greedy packing (group count, cells in groups) and give the same results."""
+    nx = nz = 40
+    d = 20.0
+    pop = synth.domain_2d(seed=synth.SEEDS[6], nx=nx, ny=nz, per_cell=100)
+    ctx, ref = _setup(sdm_mod, oracle_mod, pop, nx, nz, d)
+    ctx.set_launch_config(group_slots=slots)
+    cx, cz = synth.eddy_courant(nx, nz, d, d, 2.0, w_max=3.0)
+    for t in range(5):
+        ctx.transport(cx, cz, 2.0, sediment=True)
+        ref.transport(cx, cz, 2.0, sediment=True)
+        ctx.step(1.0, "geometric", 5, t)
+        ref.step(1.0, oracle_mod.GEOMETRIC, 5, t)
+    dev = ctx.plan()
+    other = 512 if slots == 256 else 256
+    ctx.set_launch_config(group_slots=other)
+    ctx.set_launch_config(group_slots=slots)      # host plan from the same offsets
+    host = ctx.plan()
+    assert dev == host
+    _assert_same(ctx, ref, "device plan")
+
+
 def test_transport_errors(sdm_mod):
     nx = nz = 4
     d = 10.0
