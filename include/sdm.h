@@ -18,6 +18,8 @@
  *     and takes r_k' = cbrt(gamma r_j^3 + r_k^3) (rounded to nearest), j keeps
  *     r_j and loses gamma*xi_k; when that would empty j, both SDs take the
  *     merged radius and share xi_k as floor(xi_k/2) (j) and the rest (k).
+ *     (sdm_set_rules selects the paper's own rules instead: one event when
+ *     u < p, a zero multiplicity on equal xi, and recycling.)
  *
  * Randomness is counter-based Philox4x32-10 keyed by (seed, step, cell, slot)
  * (the paper's release uses Mersenne Twister, Sect. 5.3): the shuffle key of
@@ -29,9 +31,11 @@
  * Philox(counter = (m/2, c, t, 1), same key).
  *
  * Storage order: at initialisation the SDs are stable-sorted by cell (ties in
- * input order); cell c then owns a fixed range of storage slots, local slot
- * s = 0..N_c-1.  Results are therefore a function of (inputs, seed, step
- * numbers) only: independent of launch shape, batching and mix.
+ * input order); cell c then owns a range of storage slots, local slot
+ * s = 0..N_c-1, which only a transport step changes (it re-sorts by the new
+ * cells, stable in the old storage order).  Results are therefore a function
+ * of (inputs, seed, step numbers) only: independent of launch shape, batching
+ * and mix.
  *
  * Conventions for every call:
  *   - "dev" pointers are device (HBM) pointers on the current HIP device;
