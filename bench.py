@@ -102,9 +102,9 @@ def bench_large(args):
     stream = torch.cuda.Stream()
     ctx = sdm.Context(pop.cell, pop.xi, pop.r, pop.dV, stream=stream)
     if args.launch:
-        slots, gpw, wpb, bt, xr = (int(v) for v in args.launch.split(","))
+        slots, gpw, wpb, xr = (int(v) for v in args.launch.split(","))
         ctx.set_launch_config(group_slots=slots, groups_per_wave=gpw, waves_per_block=wpb,
-                              block_threads=bt, xcd_remap=xr)
+                              xcd_remap=xr)
     elif args.autotune:
         best = ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=3)
         log(f"autotuned launch config {best.as_dict()}")
@@ -140,7 +140,7 @@ def bench_large(args):
         "data": "synthetic",
         "config": {"workload": "large_domain_1024x1024_poisson128_geometric_dt0.5",
                    "n_sd": pop.n_sd, "n_cells": pop.n_cells, "parallelism": "single_gpu",
-                   "groups": plan[0], "wave_cells": plan[1], "block_cells": plan[2],
+                   "groups": plan[0], "wave_cells": plan[1], "grid_cells": plan[2],
                    "launch": cfg},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=64.0, help="served HBM budget")
     ap.add_argument("--launch", default="",
                     help="fixed launch config group_slots,groups_per_wave,waves_per_block,"
-                         "block_threads,xcd_remap (skips the autotuner)")
+                         "xcd_remap (skips the autotuner)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "only one GPU is supported: the coalescence step would "

@@ -294,24 +294,22 @@ sdm_status sdm_transport_step(sdm_ctx *ctx, const double *cx, const double *cz, 
 sdm_status sdm_transport_get_positions(sdm_ctx *ctx, double *x_out, double *z_out);
 
 /* Launch plan of a context: number of wave-tier groups (runs of consecutive
- * cells processed by one wavefront), cells in them, and cells handled one
- * workgroup per cell (cells with more storage slots than a group holds).
- * host outputs, nullable. */
+ * cells processed by one wavefront), cells in them, and cells of the grid tier
+ * (cells with more storage slots than a group holds, each spread over many
+ * workgroups).  host outputs, nullable. */
 sdm_status sdm_get_plan(sdm_ctx *ctx, uint32_t *groups, uint32_t *wave_cells,
-                        uint32_t *block_cells);
+                        uint32_t *grid_cells);
 
 /* Launch-shape knobs; none of them changes any result.
  *   group_slots    : storage slots one wavefront handles per group (256 or
- *                    512); cells with more slots go to the workgroup tier;
+ *                    512); cells with more slots go to the grid tier;
  *   groups_per_wave: groups each wavefront takes in sequence (1..64);
  *   waves_per_block: wavefronts per workgroup of the wave tier (1, 2, 4);
- *   block_threads  : threads of the workgroup-per-cell kernel (256 or 1024);
  *   xcd_remap      : 1 = give each of the 8 XCDs a contiguous range of groups. */
 typedef struct {
     uint32_t group_slots;
     uint32_t groups_per_wave;
     uint32_t waves_per_block;
-    uint32_t block_threads;
     uint32_t xcd_remap;
 } sdm_launch_config;
 sdm_status sdm_get_launch_config(sdm_ctx *ctx, sdm_launch_config *cfg);

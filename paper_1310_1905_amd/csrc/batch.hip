@@ -106,7 +106,6 @@ struct BatchLayout {
     InstanceRec* inst;
     uint32_t* group_begin;
     uint32_t* group_end;
-    uint32_t* block_items;
     GridArrays grid;
     unsigned int* err;
     uint32_t* local_off;     // admission: offsets of the instance being added
@@ -134,7 +133,6 @@ BatchLayout batch_layout(void* ws, size_t bytes, uint64_t max_sd, uint32_t max_c
     L.inst = cv.take<InstanceRec>(max_inst);
     L.group_begin = cv.take<uint32_t>(max_cells);
     L.group_end = cv.take<uint32_t>(max_cells);
-    L.block_items = cv.take<uint32_t>(max_cells);
     carve_grid(cv, max_sd, &L.grid);
     L.err = cv.take<unsigned int>(64);
     L.local_off = cv.take<uint32_t>(uint64_t(max_cells) + 1);
@@ -162,7 +160,7 @@ struct sdm_batch {
     BatchLayout L{};
     RangePool sd_pool, cell_pool;
     std::vector<HostInstance> inst;
-    uint32_t n_groups = 0, n_block = 0;
+    uint32_t n_groups = 0;
     bool dirty = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -176,7 +174,7 @@ static sdm_status rebuild_lists(sdm_batch* b)
     for (const HostInstance& h : b->inst) {
         if (!h.live || h.n_cells == 0) continue;
         plan_cells(plan, static_cast<uint32_t>(h.cell_begin), h.cell_sizes.data(), h.n_cells,
-                   b->shape.group_slots, kGridMinSlots);
+                   b->shape.group_slots);
     }
     plan_finish(plan);
     const size_t ng = plan.group_begin.size();
@@ -186,13 +184,9 @@ static sdm_status rebuild_lists(sdm_batch* b)
         SDM_HIP(hipMemcpyAsync(b->L.group_end, plan.group_end.data(), ng * 4, hipMemcpyHostToDevice,
                                b->stream));
     }
-    if (!plan.block_cells.empty())
-        SDM_HIP(hipMemcpyAsync(b->L.block_items, plan.block_cells.data(),
-                               plan.block_cells.size() * 4, hipMemcpyHostToDevice, b->stream));
     SDM_TRY(upload_grid(b->stream, plan, &b->L.grid));
     SDM_HIP(hipStreamSynchronize(b->stream));
     b->n_groups = static_cast<uint32_t>(ng);
-    b->n_block = static_cast<uint32_t>(plan.block_cells.size());
     b->dirty = true;
     return SDM_OK;
 }
@@ -214,8 +208,8 @@ static sdm_status enqueue_step(sdm_batch* b)
     a.scr_pos = b->L.scr_pos;
     a.scr_cnt = b->L.scr_cnt;
     grid_args(b->L.grid, &a);
-    SDM_TRY(launch_step(b->stream, a, b->L.group_begin, b->L.group_end, b->n_groups,
-                        b->L.block_items, b->n_block, b->shape, true, false));
+    SDM_TRY(launch_step(b->stream, a, b->L.group_begin, b->L.group_end, b->n_groups, b->shape,
+                        true, false));
     hipLaunchKernelGGL(k_advance_instances, dim3(grid_for(b->max_inst, 256, 1024)), dim3(256), 0,
                        b->stream, b->L.inst, b->max_inst);
     SDM_LAUNCHED();

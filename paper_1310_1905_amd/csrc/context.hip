@@ -20,7 +20,6 @@ struct CtxLayout {
     double* dV;
     uint32_t* group_begin;
     uint32_t* group_end;
-    uint32_t* block_items;
     GridArrays grid;
     unsigned long long* stats;
     unsigned int* err;
@@ -28,7 +27,7 @@ struct CtxLayout {
     uint32_t* probe_order;
     uint32_t* probe_nlive;
     unsigned long long* probe_max;
-    // scratch (workgroup-tier sort arrays during steps; sort-by-cell arrays during init)
+    // scratch (grid-tier sort arrays during steps; sort-by-cell arrays during init)
     uint64_t* scr_kv;
     uint64_t* scr_tmp;
     uint32_t* scr_pos;
@@ -48,7 +47,6 @@ CtxLayout layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t c)
     L.dV = cv.take<double>(c);
     L.group_begin = cv.take<uint32_t>(c);
     L.group_end = cv.take<uint32_t>(c);
-    L.block_items = cv.take<uint32_t>(c);
     carve_grid(cv, n, &L.grid);
     L.stats = cv.take<unsigned long long>(uint64_t(kStatSlots) * kStatStride);
     L.err = cv.take<unsigned int>(64);
@@ -111,8 +109,7 @@ sdm_status upload_plan(sdm_ctx* x)
         x->sizes_stale = false;
     }
     Plan plan;
-    plan_cells(plan, 0, x->sizes.data(), x->n_cells, x->shape.group_slots,
-               grid_threshold(x->sizes.data(), x->n_cells, x->shape.group_slots));
+    plan_cells(plan, 0, x->sizes.data(), x->n_cells, x->shape.group_slots);
     plan_finish(plan);
     const size_t ng = plan.group_begin.size();
     if (ng) {
@@ -121,14 +118,10 @@ sdm_status upload_plan(sdm_ctx* x)
         SDM_HIP(hipMemcpyAsync(x->group_end, plan.group_end.data(), ng * 4, hipMemcpyHostToDevice,
                                x->stream));
     }
-    if (!plan.block_cells.empty())
-        SDM_HIP(hipMemcpyAsync(x->block_items, plan.block_cells.data(), plan.block_cells.size() * 4,
-                               hipMemcpyHostToDevice, x->stream));
     SDM_TRY(upload_grid(x->stream, plan, &x->grid));
     SDM_HIP(hipStreamSynchronize(x->stream));
     x->n_groups = static_cast<uint32_t>(ng);
     x->n_wave_cells = plan.wave_cells;
-    x->n_block = static_cast<uint32_t>(plan.block_cells.size());
     return SDM_OK;
 }
 
@@ -218,7 +211,6 @@ extern "C" sdm_status sdm_init(sdm_ctx** out, void* stream, void* workspace, siz
     x->dV = L.dV;
     x->group_begin = L.group_begin;
     x->group_end = L.group_end;
-    x->block_items = L.block_items;
     x->grid = L.grid;
     x->stats = L.stats;
     x->err = L.err;
@@ -276,8 +268,8 @@ static sdm_status enqueue_recycle(sdm_ctx* x)
 
 static sdm_status launch(sdm_ctx* x, const StepArgs& a, bool perm)
 {
-    return launch_step(x->stream, a, x->group_begin, x->group_end, x->n_groups, x->block_items,
-                       x->n_block, x->shape, false, perm);
+    return launch_step(x->stream, a, x->group_begin, x->group_end, x->n_groups, x->shape, false,
+                       perm);
 }
 
 extern "C" sdm_status sdm_coalesce_step(sdm_ctx* x, double dt, sdm_kernel kernel, uint64_t seed,
@@ -553,12 +545,12 @@ extern "C" sdm_status sdm_get_layout(sdm_ctx* x, const uint32_t** offsets,
 }
 
 extern "C" sdm_status sdm_get_plan(sdm_ctx* x, uint32_t* groups, uint32_t* wave_cells,
-                                   uint32_t* block_cells)
+                                   uint32_t* grid_cells)
 {
     SDM_TRY(check_ctx(x));
     if (groups) *groups = x->n_groups;
     if (wave_cells) *wave_cells = x->n_wave_cells;
-    if (block_cells) *block_cells = x->n_block + x->grid.n_grid;
+    if (grid_cells) *grid_cells = x->grid.n_grid;
     return SDM_OK;
 }
 
@@ -568,7 +560,6 @@ static LaunchShape from_cfg(const sdm_launch_config& c)
     s.group_slots = c.group_slots;
     s.groups_per_wave = c.groups_per_wave;
     s.waves_per_block = c.waves_per_block;
-    s.block_threads = c.block_threads;
     s.xcd_remap = c.xcd_remap;
     return s;
 }
@@ -578,7 +569,6 @@ static void to_cfg(const LaunchShape& s, sdm_launch_config* c)
     c->group_slots = s.group_slots;
     c->groups_per_wave = s.groups_per_wave;
     c->waves_per_block = s.waves_per_block;
-    c->block_threads = s.block_threads;
     c->xcd_remap = s.xcd_remap;
 }
 

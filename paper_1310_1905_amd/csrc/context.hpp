@@ -55,7 +55,6 @@ struct sdm_ctx {
     double* dV = nullptr;
     uint32_t* group_begin = nullptr;
     uint32_t* group_end = nullptr;
-    uint32_t* block_items = nullptr;
     sdm::GridArrays grid;
     unsigned long long* stats = nullptr;
     unsigned int* err = nullptr;
@@ -69,7 +68,7 @@ struct sdm_ctx {
     // plan
     std::vector<uint32_t> sizes;   // storage slots per cell (host copy)
     bool sizes_stale = false;      // sizes behind the device offsets (device-planned)
-    uint32_t n_groups = 0, n_wave_cells = 0, n_block = 0;
+    uint32_t n_groups = 0, n_wave_cells = 0;
     sdm::LaunchShape shape;
     uint32_t rules = 0;   // sdm_rule flags applied by every step
     // admission sort scratch (shares the step scratch region; reused by transport)

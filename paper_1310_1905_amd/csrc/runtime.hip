@@ -130,7 +130,7 @@ sdm_status radix_sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, u
 
 // ------------------------------------------------------------ step plan
 void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_cells,
-                uint32_t group_slots, uint32_t grid_min)
+                uint32_t group_slots)
 {
     uint32_t g_start = 0, g_slots = 0;
     bool open = false;
@@ -143,13 +143,8 @@ void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_
                 plan.group_end.push_back(c);
                 open = false;
             }
-            if (n > grid_min) {
-                plan.grid.push_back(GridCell{c, 0, 0, 0, 0, 0, 0, 0});
-                plan.grid_sizes.push_back(n);
-            } else {
-                plan.block_cells.push_back(c);
-                plan.block_sizes.push_back(n);
-            }
+            plan.grid.push_back(GridCell{c, 0, 0, 0, 0, 0, 0, 0});
+            plan.grid_sizes.push_back(n);
             continue;
         }
         if (open && (g_slots + n > group_slots || c - g_start >= static_cast<uint32_t>(kGroupMaxCells))) {
@@ -171,63 +166,55 @@ void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_
     }
 }
 
-uint32_t grid_threshold(const uint32_t* sizes, uint32_t n_cells, uint32_t group_slots)
-{
-    uint32_t big = 0;
-    for (uint32_t i = 0; i < n_cells && big < kFewBigCells; ++i) big += sizes[i] > group_slots;
-    return big < kFewBigCells ? kGridMinSlotsFew : kGridMinSlots;
-}
-
 void plan_finish(Plan& plan)
 {
-    // grid tier: bucket count 2^(floor(log2 N) - 1) <= N/2, chunk and tile tables
+    // grid tier: digit bits cb = ceil(log2 N) - kGridBucketLg (at most
+    // kGridMaxDigitBits) and slot chunks of 2^lgc slots, lgc = max(11, lgN - 9),
+    // keep the count table 2^cb * ncol below N, so that it and its sentinel fit
+    // the cell's scr_cnt range
     uint32_t tile = 0;
     for (uint32_t i = 0; i < plan.grid.size(); ++i) {
         const uint32_t n = plan.grid_sizes[i];
-        const uint32_t lg = 31u - static_cast<uint32_t>(__builtin_clz(n)) - 1u;
+        const uint32_t lgn = 32u - static_cast<uint32_t>(__builtin_clz(n - 1u));
         GridCell& gc = plan.grid[i];
-        gc.lg = lg;
-        gc.nb = 1u << lg;
+        gc.lgc = std::max(kGridChunkLg, lgn > 9u ? lgn - 9u : 0u);
+        gc.ncol = static_cast<uint32_t>((static_cast<uint64_t>(n) + (1u << gc.lgc) - 1u) >> gc.lgc);
+        gc.cb = std::min(lgn > kGridBucketLg ? lgn - kGridBucketLg : 0u, kGridMaxDigitBits);
+        while (gc.cb > 0 && (static_cast<uint64_t>(gc.ncol) << gc.cb) + 1u > n) --gc.cb;
+        gc.nb = gc.ncol << gc.cb;
         gc.tile0 = tile;
         gc.ntiles = (gc.nb + kGridTile - 1) / kGridTile;
+        gc.live = 0;
         for (uint32_t t = 0; t < gc.ntiles; ++t) plan.gtile.push_back(make_uint2(i, t * kGridTile));
         tile += gc.ntiles;
-        for (uint32_t s0 = 0; s0 < n; s0 += kGridChunk) plan.gchunk.push_back(make_uint2(i, s0));
+        for (uint64_t s0 = 0; s0 < n; s0 += 1u << gc.lgc)
+            plan.gchunk.push_back(make_uint2(i, static_cast<uint32_t>(s0)));
+        for (uint32_t d = 0; d < (1u << gc.cb); ++d) plan.gbucket.push_back(make_uint2(i, d));
         for (uint32_t y = 0; y < n / 2; y += kGridPairChunk) plan.gpchunk.push_back(make_uint2(i, y));
     }
-    // workgroup tier: largest cells first, so the long ones start early
-    std::vector<uint32_t> idx(plan.block_cells.size());
-    for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
-    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
-        return plan.block_sizes[a] > plan.block_sizes[b];
-    });
-    std::vector<uint32_t> cells(idx.size()), sizes(idx.size());
-    for (size_t i = 0; i < idx.size(); ++i) {
-        cells[i] = plan.block_cells[idx[i]];
-        sizes[i] = plan.block_sizes[idx[i]];
-    }
-    plan.block_cells.swap(cells);
-    plan.block_sizes.swap(sizes);
 }
 
 bool shape_valid(const LaunchShape& c)
 {
     const bool waves_ok = c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4;
-    const bool block_ok = c.block_threads == 256 || c.block_threads == 1024;
     const bool slots_ok = c.group_slots == 256 || c.group_slots == 512;
-    return waves_ok && block_ok && slots_ok && c.groups_per_wave >= 1 && c.groups_per_wave <= 64 &&
+    return waves_ok && slots_ok && c.groups_per_wave >= 1 && c.groups_per_wave <= 64 &&
            c.xcd_remap <= 1;
 }
 
 void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g)
 {
-    g->cap_cells = n_sd / (kGridMinSlotsFew + 1) + 1;
+    // a grid cell has more slots than the smallest group (256)
+    g->cap_cells = n_sd / 257 + 1;
     g->cap_chunks = n_sd / kGridChunk + g->cap_cells;
-    g->cap_tiles = n_sd / 2 / kGridTile + g->cap_cells;
+    g->cap_tiles = n_sd / kGridTile + g->cap_cells;
+    // 2^cb <= 2^(ceil(log2 N) - 10) < N / 512
+    g->cap_buckets = n_sd / (1u << (kGridBucketLg - 1)) + g->cap_cells;
     g->cap_pchunks = n_sd / 2 / kGridPairChunk + g->cap_cells;
     g->gcell = c.take<GridCell>(g->cap_cells);
     g->gchunk = c.take<uint2>(g->cap_chunks);
     g->gtile = c.take<uint2>(g->cap_tiles);
+    g->gbucket = c.take<uint2>(g->cap_buckets);
     g->gpchunk = c.take<uint2>(g->cap_pchunks);
     g->gtilesum = c.take<uint32_t>(g->cap_tiles);
 }
@@ -235,7 +222,8 @@ void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g)
 sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
 {
     if (plan.grid.size() > g->cap_cells || plan.gchunk.size() > g->cap_chunks ||
-        plan.gtile.size() > g->cap_tiles || plan.gpchunk.size() > g->cap_pchunks) {
+        plan.gtile.size() > g->cap_tiles || plan.gbucket.size() > g->cap_buckets ||
+        plan.gpchunk.size() > g->cap_pchunks) {
         set_error("grid-tier tables exceed their capacity");
         return SDM_ENOMEM;
     }
@@ -246,12 +234,15 @@ sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
                                hipMemcpyHostToDevice, s));
         SDM_HIP(hipMemcpyAsync(g->gtile, plan.gtile.data(), plan.gtile.size() * sizeof(uint2),
                                hipMemcpyHostToDevice, s));
+        SDM_HIP(hipMemcpyAsync(g->gbucket, plan.gbucket.data(), plan.gbucket.size() * sizeof(uint2),
+                               hipMemcpyHostToDevice, s));
         SDM_HIP(hipMemcpyAsync(g->gpchunk, plan.gpchunk.data(), plan.gpchunk.size() * sizeof(uint2),
                                hipMemcpyHostToDevice, s));
     }
     g->n_grid = static_cast<uint32_t>(plan.grid.size());
     g->n_gchunk = static_cast<uint32_t>(plan.gchunk.size());
     g->n_gtile = static_cast<uint32_t>(plan.gtile.size());
+    g->n_gbucket = static_cast<uint32_t>(plan.gbucket.size());
     g->n_gpchunk = static_cast<uint32_t>(plan.gpchunk.size());
     return SDM_OK;
 }
@@ -264,6 +255,8 @@ void grid_args(const GridArrays& g, StepArgs* a)
     a->n_gchunk = g.n_gchunk;
     a->gtile = g.gtile;
     a->n_gtile = g.n_gtile;
+    a->gbucket = g.gbucket;
+    a->n_gbucket = g.n_gbucket;
     a->gpchunk = g.gpchunk;
     a->n_gpchunk = g.n_gpchunk;
     a->gtilesum = g.gtilesum;
@@ -273,9 +266,7 @@ template <bool BATCHED, bool PERM>
 static sdm_status launch_grid(hipStream_t s, const StepArgs& a)
 {
     const dim3 blk(kGridBlock);
-    hipLaunchKernelGGL(k_grid_zero, dim3(a.n_gtile), blk, 0, s, a);
-    SDM_LAUNCHED();
-    hipLaunchKernelGGL((k_grid_keys<BATCHED>), dim3(a.n_gchunk), blk, 0, s, a);
+    hipLaunchKernelGGL((k_grid_digits<BATCHED, false>), dim3(a.n_gchunk), blk, 0, s, a);
     SDM_LAUNCHED();
     hipLaunchKernelGGL(k_grid_tile_sums, dim3(a.n_gtile), blk, 0, s, a);
     SDM_LAUNCHED();
@@ -291,9 +282,9 @@ static sdm_status launch_grid(hipStream_t s, const StepArgs& a)
     SDM_LAUNCHED();
     hipLaunchKernelGGL(k_grid_tile_scan, dim3(a.n_gtile), blk, 0, s, a);
     SDM_LAUNCHED();
-    hipLaunchKernelGGL((k_grid_scatter<BATCHED>), dim3(a.n_gchunk), blk, 0, s, a);
+    hipLaunchKernelGGL((k_grid_digits<BATCHED, true>), dim3(a.n_gchunk), blk, 0, s, a);
     SDM_LAUNCHED();
-    hipLaunchKernelGGL((k_grid_rank<BATCHED>), dim3(a.n_gchunk), blk, 0, s, a);
+    hipLaunchKernelGGL(k_grid_bucket_sort, dim3(a.n_gbucket), blk, 0, s, a);
     SDM_LAUNCHED();
     hipLaunchKernelGGL((k_grid_pairs<BATCHED, PERM>), dim3(a.n_gpchunk), blk, 0, s, a);
     SDM_LAUNCHED();
@@ -323,24 +314,6 @@ static sdm_status launch_wave(hipStream_t s, const StepArgs& a, uint32_t n_group
 }
 
 template <bool BATCHED, bool PERM>
-static sdm_status launch_block(hipStream_t s, const StepArgs& a, uint32_t n_items,
-                               const LaunchShape& sh)
-{
-    const uint32_t blocks = n_items < 8192u ? n_items : 8192u;
-    switch (sh.block_threads) {
-    case 256:
-        hipLaunchKernelGGL((k_block_cells<256, BATCHED, PERM>), dim3(blocks), dim3(256), 0, s, a);
-        break;
-    case 1024:
-        hipLaunchKernelGGL((k_block_cells<1024, BATCHED, PERM>), dim3(blocks), dim3(1024), 0, s, a);
-        break;
-    default: set_error("block_threads must be 256 or 1024"); return SDM_EINVAL;
-    }
-    SDM_LAUNCHED();
-    return SDM_OK;
-}
-
-template <bool BATCHED, bool PERM>
 static sdm_status launch_wave_any(hipStream_t s, const StepArgs& a, uint32_t n_groups,
                                   const LaunchShape& sh)
 {
@@ -351,8 +324,8 @@ static sdm_status launch_wave_any(hipStream_t s, const StepArgs& a, uint32_t n_g
 }
 
 sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* group_begin,
-                       const uint32_t* group_end, uint32_t n_groups, const uint32_t* block_items,
-                       uint32_t n_block, const LaunchShape& shape, bool batched, bool perm)
+                       const uint32_t* group_end, uint32_t n_groups, const LaunchShape& shape,
+                       bool batched, bool perm)
 {
     if (n_groups > 0) {
         StepArgs a = base;
@@ -365,15 +338,6 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
                                   : launch_wave_any<true, false>(s, a, n_groups, shape));
         else SDM_TRY(perm ? launch_wave_any<false, true>(s, a, n_groups, shape)
                           : launch_wave_any<false, false>(s, a, n_groups, shape));
-    }
-    if (n_block > 0) {
-        StepArgs a = base;
-        a.items = block_items;
-        a.n_items = n_block;
-        if (batched) SDM_TRY(perm ? launch_block<true, true>(s, a, n_block, shape)
-                                  : launch_block<true, false>(s, a, n_block, shape));
-        else SDM_TRY(perm ? launch_block<false, true>(s, a, n_block, shape)
-                          : launch_block<false, false>(s, a, n_block, shape));
     }
     if (base.n_grid > 0) {
         if (batched) SDM_TRY(perm ? launch_grid<true, true>(s, base) : launch_grid<true, false>(s, base));

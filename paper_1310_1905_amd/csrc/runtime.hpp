@@ -121,19 +121,18 @@ struct LaunchShape {
     uint32_t group_slots = 512;      // storage slots per wave-tier group (256 or 512)
     uint32_t groups_per_wave = 2;
     uint32_t waves_per_block = 1;
-    uint32_t block_threads = 256;
     uint32_t xcd_remap = 0;
 };
 
-// Work lists of one step: wave-tier groups of consecutive cells and
-// workgroup-tier cells (largest first).
+// Work lists of one step: wave-tier groups of consecutive cells and the
+// grid-tier cells with their chunk, table-tile, bucket and pair-chunk lists.
 struct Plan {
-    std::vector<uint32_t> group_begin, group_end, block_cells, block_sizes;
+    std::vector<uint32_t> group_begin, group_end;
     uint32_t wave_cells = 0;
     // grid tier
     std::vector<GridCell> grid;
     std::vector<uint32_t> grid_sizes;
-    std::vector<uint2> gchunk, gtile, gpchunk;
+    std::vector<uint2> gchunk, gtile, gbucket, gpchunk;
 };
 
 // Device arrays of the grid tier (inside a workspace) and their capacities.
@@ -141,31 +140,30 @@ struct GridArrays {
     GridCell* gcell = nullptr;
     uint2* gchunk = nullptr;
     uint2* gtile = nullptr;
+    uint2* gbucket = nullptr;
     uint2* gpchunk = nullptr;
     uint32_t* gtilesum = nullptr;
-    uint64_t cap_cells = 0, cap_chunks = 0, cap_tiles = 0, cap_pchunks = 0;
-    uint32_t n_grid = 0, n_gchunk = 0, n_gtile = 0, n_gpchunk = 0;
+    uint64_t cap_cells = 0, cap_chunks = 0, cap_tiles = 0, cap_buckets = 0, cap_pchunks = 0;
+    uint32_t n_grid = 0, n_gchunk = 0, n_gtile = 0, n_gbucket = 0, n_gpchunk = 0;
 };
 void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g);
 sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g);
 void grid_args(const GridArrays& g, StepArgs* a);
 
-// Append to `plan` the cells [c_begin, c_end) whose storage-slot counts are
-// sizes[0..): cells above shape.group_slots go to the workgroup tier, the rest
+// Append to `plan` the cells [c_begin, c_begin + n_cells) whose storage-slot
+// counts are sizes[0..): cells above group_slots go to the grid tier, the rest
 // are packed greedily into groups of at most group_slots slots and
 // kGroupMaxCells cells.
 void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_cells,
-                uint32_t group_slots, uint32_t grid_min);
-// Size above which a cell goes to the grid tier: kGridMinSlotsFew when fewer than
-// kFewBigCells cells exceed group_slots, else kGridMinSlots.
-uint32_t grid_threshold(const uint32_t* sizes, uint32_t n_cells, uint32_t group_slots);
+                uint32_t group_slots);
+// Per-cell parameters and work lists of the grid tier.
 void plan_finish(Plan& plan);
 
-// Enqueue the wave-tier, workgroup-tier and grid-tier kernels for one step
-// (base carries the grid-tier arrays, see grid_args).
+// Enqueue the wave-tier and grid-tier kernels for one step (base carries the
+// grid-tier arrays, see grid_args).
 sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* group_begin,
-                       const uint32_t* group_end, uint32_t n_groups, const uint32_t* block_items,
-                       uint32_t n_block, const LaunchShape& shape, bool batched, bool perm);
+                       const uint32_t* group_end, uint32_t n_groups, const LaunchShape& shape,
+                       bool batched, bool perm);
 
 bool shape_valid(const LaunchShape& sh);
 

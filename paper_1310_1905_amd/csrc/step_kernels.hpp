@@ -14,12 +14,13 @@
 // entries on average, so the sort is O(n) and its result is independent of
 // the atomic arrival order.
 //
-// Two kernels cover all cell sizes with identical results:
+// Two tiers cover all cell sizes with identical results:
 //   k_wave_groups -- one 64-lane wavefront per group of consecutive cells
 //                    (at most CAP storage slots in all), everything in LDS;
-//   k_block_cells -- one workgroup per cell for larger cells, with the sort
-//                    arrays in a global scratch area (L2-resident) that is
-//                    indexed like the super-droplet arrays.
+//   grid tier     -- cells with more slots than a group holds, each spread
+//                    over many workgroups, with the sort arrays in a global
+//                    scratch area that is indexed like the super-droplet
+//                    arrays (a two-level digit sort, see below).
 #pragma once
 
 #include "device_math.hpp"
@@ -54,8 +55,6 @@ struct StepArgs {
     uint64_t* xi;                 // storage-order multiplicities
     double* r;                    // storage-order radii
     uint64_t n_sd;                // length of xi and r
-    const uint32_t* items;        // workgroup tier: cell-table indices
-    uint32_t n_items;
     const uint32_t* group_begin;  // wave tier: first cell of each group
     const uint32_t* group_end;    // one past the last cell
     uint32_t n_groups;
@@ -88,24 +87,29 @@ struct StepArgs {
     uint32_t n_grid;
     const uint2* gchunk;          // (grid cell, first slot) per slot chunk
     uint32_t n_gchunk;
-    const uint2* gtile;           // (grid cell, first bucket) per bucket tile
+    const uint2* gtile;           // (grid cell, first entry) per count-table tile
     uint32_t n_gtile;
+    const uint2* gbucket;         // (grid cell, digit) per digit bucket
+    uint32_t n_gbucket;
     const uint2* gpchunk;         // (grid cell, first pair) per pair chunk
     uint32_t n_gpchunk;
     uint32_t* gtilesum;
 };
 
-// One cell of the grid tier.  lg and nb depend on the storage-slot count only
-// (any bucket count gives the same order); live and tile offsets are written
-// during the step.
+// One cell of the grid tier.  Everything but `live` depends on the storage-slot
+// count only (any digit width gives the same order); live is written during the
+// step.  The count table lives in the cell's scr_cnt range: entry d * ncol + c
+// counts the live slots of chunk c whose key has digit d, and entry nb is the
+// sentinel (the live count) after the scan.
 struct GridCell {
     uint32_t cell;     // cell-table index
-    uint32_t lg;       // bucket bits
-    uint32_t nb;       // 2^lg buckets (<= N/2)
-    uint32_t tile0;    // first bucket tile
+    uint32_t cb;       // digit bits: a digit is the top cb bits of a key
+    uint32_t lgc;      // a slot chunk (one table column) is 2^lgc slots
+    uint32_t ncol;     // slot chunks
+    uint32_t nb;       // table entries, 2^cb * ncol (< storage slots)
+    uint32_t tile0;    // first table tile
     uint32_t ntiles;
     uint32_t live;     // live SDs this step
-    uint32_t pad0, pad1;
 };
 
 // Resolved per-cell parameters.
@@ -686,9 +690,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
     }
 }
 
-// ---------------------------------------------------------------------------
-// Workgroup tier: one workgroup per cell, any number of storage slots.
-// ---------------------------------------------------------------------------
+// Sum of v over a workgroup of BLOCK threads (every thread gets it).
 template <int BLOCK>
 __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* s_red)
 {
@@ -705,196 +707,72 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* s_red)
     return t;
 }
 
-// In-place exclusive scan of arr[0..nb) (global), arr[nb] = total.
-template <int BLOCK>
-__device__ void block_exclusive_scan(uint32_t* arr, uint32_t nb, uint32_t* s_red)
-{
-    constexpr int W = BLOCK / kWave;
-    const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < nb; base += BLOCK) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t v = i < nb ? arr[i] : 0u;
-        const uint32_t incl_w = wave_inclusive_sum(v, lane);
-        if (lane == kWave - 1) s_red[wv] = incl_w;
-        __syncthreads();
-        uint32_t before = 0, total = 0;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            const uint32_t t = s_red[w];
-            before += (static_cast<uint32_t>(w) < wv) ? t : 0u;
-            total += t;
-        }
-        if (i < nb) arr[i] = carry + before + incl_w - v;
-        carry += total;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) arr[nb] = carry;
-}
-
-template <int BLOCK, bool BATCHED, bool PERM>
-__global__ __launch_bounds__(BLOCK) void k_block_cells(const StepArgs a)
-{
-    __shared__ uint32_t s_red[BLOCK / kWave];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & (kWave - 1);
-    unsigned long long pair_acc = 0, coll_acc = 0;
-
-    for (uint64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
-        const uint32_t c = a.items ? a.items[it] : static_cast<uint32_t>(it);
-        const CellJob j = resolve_cell<BATCHED>(a, c);
-        const uint32_t N = j.n_slots;
-        const uint64_t* xi = a.xi + j.off;
-
-        // (1) live count
-        uint32_t cnt = 0;
-        for (uint32_t s = tid; s < N; s += BLOCK) cnt += xi[s] != 0 ? 1u : 0u;
-        const uint32_t n = block_sum<BLOCK>(cnt, s_red);
-        if (n < 2) {
-            if constexpr (PERM) {
-                if (tid == 0) a.nlive_out[c] = n;
-                for (uint32_t s = tid; s < N; s += BLOCK)
-                    if (xi[s] != 0) a.perm_out[j.off] = s;
-            }
-            continue;
-        }
-        // about two keys per bucket; the bucket array fits in n entries
-        const uint32_t lg = ceil_log2(n) - 1u;
-        const uint32_t nb = 1u << lg;
-        uint32_t* cntp = a.scr_cnt + j.off;
-        uint64_t* kv = a.scr_kv + j.off;
-        uint64_t* tmp = a.scr_tmp + j.off;
-        uint32_t* pos = a.scr_pos + j.off;
-
-        for (uint32_t i = tid; i <= nb; i += BLOCK) cntp[i] = 0;
-        __syncthreads();
-
-        // (2) keys and bucket counts
-        for (uint32_t q = tid; 4 * q < N; q += BLOCK) {
-            const Words4 w = philox4x32_10(q, j.rng_cell, j.step, kTagShuffle, j.k0, j.k1);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const uint32_t s = 4 * q + t;
-                if (s < N && xi[s] != 0) {
-                    const uint32_t arr = atomicAdd(&cntp[bucket_of(w.w[t], lg)], 1u);
-                    tmp[s] = (static_cast<uint64_t>(w.w[t]) << 32) | arr;
-                }
-            }
-        }
-        __syncthreads();
-        block_exclusive_scan<BLOCK>(cntp, nb, s_red);
-        __syncthreads();
-
-        // scatter
-        for (uint32_t s = tid; s < N; s += BLOCK) {
-            if (xi[s] != 0) {
-                const uint64_t t = tmp[s];
-                const uint32_t key = static_cast<uint32_t>(t >> 32);
-                const uint32_t p = cntp[bucket_of(key, lg)] + static_cast<uint32_t>(t);
-                kv[p] = (static_cast<uint64_t>(key) << 32) | s;
-            }
-        }
-        __syncthreads();
-
-        // rank inside buckets
-        for (uint32_t s = tid; s < N; s += BLOCK) {
-            if (xi[s] != 0) {
-                const uint32_t key = static_cast<uint32_t>(tmp[s] >> 32);
-                const uint32_t b = bucket_of(key, lg);
-                const uint32_t lo = cntp[b], hi = cntp[b + 1];
-                const uint64_t me = (static_cast<uint64_t>(key) << 32) | s;
-                uint32_t rank = 0;
-                for (uint32_t e = lo; e < hi; ++e) rank += (kv[e] < me) ? 1u : 0u;
-                pos[lo + rank] = s;
-            }
-        }
-        __syncthreads();
-
-        if constexpr (PERM) {
-            for (uint32_t i = tid; i < n; i += BLOCK) a.perm_out[j.off + i] = pos[i];
-            if (tid == 0) a.nlive_out[c] = n;
-            __syncthreads();
-            continue;
-        }
-
-        // (3) pairs
-        const uint32_t npairs = n >> 1;
-        const double scale = upscale_factor(n);
-        uint32_t coll = 0;
-        for (uint32_t m = tid; m < npairs; m += BLOCK) {
-            const double u = pair_uniform(m, j.rng_cell, j.step, j.k0, j.k1);
-            const uint32_t sa = pos[2 * m], sb = pos[2 * m + 1];
-            const uint64_t xa = xi[sa], xb = xi[sb];
-            const double ra = a.r[j.off + sa], rb = a.r[j.off + sb];
-            if (collide_pair_global(a, j, scale, u, sa, sb, xa, xb, ra, rb)) ++coll;
-        }
-        const uint32_t cell_coll = block_sum<BLOCK>(coll, s_red);
-        if constexpr (BATCHED) {
-            if (tid == 0) add_counts(a, true, j.inst, 0, npairs, cell_coll);
-        } else {
-            pair_acc += npairs;
-            coll_acc += cell_coll;
-        }
-        (void)lane;
-    }
-    if constexpr (!BATCHED && !PERM) {
-        if (tid == 0 && (pair_acc || coll_acc))
-            add_counts(a, false, 0, blockIdx.x, pair_acc, coll_acc);
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Grid tier: cells above kGridMinSlots storage slots (kGridMinSlotsFew when a
-// context has fewer than kFewBigCells cells beyond the wave tier), each spread over many
-// workgroups.  The step is a sequence of launches over all grid cells at once:
-// zero the bucket counters -> keys and bucket counts (global atomics) -> tile
-// sums -> per-cell scan of tile sums -> tile scans -> scatter -> in-bucket rank
-// -> pair tests.  Same algorithm and results as the other tiers.
+// Grid tier: every cell with more storage slots than a wave-tier group holds,
+// each spread over many workgroups.  The order by (key, slot) is found in two
+// levels:
+//   coarse: each slot chunk counts the digits (top cb key bits) of its live
+//     slots in LDS into its column of a digit-major count table; after an
+//     exclusive scan of the table every (digit, chunk) run has its place, and
+//     each chunk writes its (key, slot) words there, so that every digit bucket
+//     (about 512 to 1024 entries) is contiguous and the buckets are in order;
+//   fine: one workgroup per bucket splits it by the next key bits into
+//     sub-buckets of one or two entries on average, in LDS, and ranks each
+//     entry within its sub-bucket.
+// The launches cover all grid cells at once: digit counts -> table tile sums
+// -> per-cell scan of the tile sums -> table tile scans -> placement -> bucket
+// sorts -> pair tests.  Same order and results as the other tiers.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kGridMinSlots = 16384;
-// With few cells above the wave-tier capacity, one workgroup per cell leaves most
-// of the chip idle; such contexts send cells from this size on to the grid tier.
-constexpr uint32_t kGridMinSlotsFew = 4096;
-constexpr uint32_t kFewBigCells = 256;
 constexpr int kGridBlock = 256;
-constexpr uint32_t kGridChunk = 2048;     // slots per slot chunk (multiple of 4)
-constexpr uint32_t kGridTile = 4096;      // buckets per bucket tile
+constexpr uint32_t kGridChunkLg = 11;     // smallest slot chunk, 2048 slots
+constexpr uint32_t kGridChunk = 1u << kGridChunkLg;
+constexpr uint32_t kGridBucketLg = 10;    // cb = ceil(log2 N) - 10: <= 1024 per bucket on average
+constexpr uint32_t kGridMaxDigitBits = 12;
+constexpr uint32_t kGridMaxDigits = 1u << kGridMaxDigitBits;
+constexpr uint32_t kGridTile = 4096;      // table entries per tile
+constexpr uint32_t kGridSortCap = 2048;   // larger buckets are ordered through scr_tmp
+constexpr uint32_t kGridSubLg = 10;       // at most 2^10 sub-buckets per bucket
 constexpr uint32_t kGridPairChunk = 2048; // pairs per pair chunk
 
-static __global__ __launch_bounds__(kGridBlock) void k_grid_zero(const StepArgs a)
+// Digit counts (PLACE = false) or placement (PLACE = true) of one slot chunk.
+// Placement starts each digit's cursor at the chunk's scanned table entry; the
+// order within a (digit, chunk) run is arrival order and does not matter, the
+// bucket sort orders it exactly.
+template <bool BATCHED, bool PLACE>
+__global__ __launch_bounds__(kGridBlock) void k_grid_digits(const StepArgs a)
 {
-    const uint2 t = a.gtile[blockIdx.x];
-    GridCell& gc = a.gcell[t.x];
-    const uint32_t off = a.off_begin[gc.cell];
-    const uint32_t end = min(t.y + kGridTile, gc.nb + 1);   // includes the sentinel slot
-    for (uint32_t b = t.y + threadIdx.x; b < end; b += kGridBlock) a.scr_cnt[off + b] = 0;
-    if (t.y == 0 && threadIdx.x == 0) gc.live = 0;
-}
-
-template <bool BATCHED>
-__global__ __launch_bounds__(kGridBlock) void k_grid_keys(const StepArgs a)
-{
-    __shared__ uint32_t s_red[kGridBlock / kWave];
+    __shared__ uint32_t s_cnt[kGridMaxDigits];
     const uint2 ch = a.gchunk[blockIdx.x];
-    GridCell& gc = a.gcell[ch.x];
+    const GridCell& gc = a.gcell[ch.x];
     const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
-    const uint32_t lg = gc.lg;
-    const uint32_t q_end = min(ch.y + kGridChunk, j.n_slots + 3u) / 4u;
-    uint32_t live = 0;
+    const uint32_t cb = gc.cb, D = 1u << cb, ncol = gc.ncol, col = ch.y >> gc.lgc;
+    uint32_t* tbl = a.scr_cnt + j.off;
+    for (uint32_t d = threadIdx.x; d < D; d += kGridBlock) s_cnt[d] = PLACE ? tbl[d * ncol + col] : 0u;
+    __syncthreads();
+    const uint32_t s_end = min(ch.y + (1u << gc.lgc), j.n_slots);
+    const uint32_t q_end = (s_end + 3u) / 4u;
+    const uint64_t* xi = a.xi + j.off;
     for (uint32_t q = ch.y / 4u + threadIdx.x; q < q_end; q += kGridBlock) {
+        bool live[4];
+#pragma unroll
+        for (uint32_t t = 0; t < 4; ++t) live[t] = 4 * q + t < s_end && xi[4 * q + t] != 0;
         const Words4 w = philox4x32_10(q, j.rng_cell, j.step, kTagShuffle, j.k0, j.k1);
 #pragma unroll
         for (uint32_t t = 0; t < 4; ++t) {
-            const uint32_t s = 4 * q + t;
-            if (s < j.n_slots && a.xi[j.off + s] != 0) {
-                const uint32_t arr = atomicAdd(&a.scr_cnt[j.off + bucket_of(w.w[t], lg)], 1u);
-                a.scr_tmp[j.off + s] = (static_cast<uint64_t>(w.w[t]) << 32) | arr;
-                ++live;
+            if (!live[t]) continue;
+            const uint32_t d = bucket_of(w.w[t], cb);
+            if constexpr (PLACE) {
+                const uint32_t p = atomicAdd(&s_cnt[d], 1u);
+                a.scr_kv[j.off + p] = (static_cast<uint64_t>(w.w[t]) << 32) | (4 * q + t);
+            } else {
+                atomicAdd(&s_cnt[d], 1u);
             }
         }
     }
-    const uint32_t tot = block_sum<kGridBlock>(live, s_red);
-    if (threadIdx.x == 0 && tot) atomicAdd(&gc.live, tot);
+    if constexpr (!PLACE) {
+        __syncthreads();
+        for (uint32_t d = threadIdx.x; d < D; d += kGridBlock) tbl[d * ncol + col] = s_cnt[d];
+    }
 }
 
 static __global__ __launch_bounds__(kGridBlock) void k_grid_tile_sums(const StepArgs a)
@@ -915,7 +793,7 @@ template <bool BATCHED>
 __global__ __launch_bounds__(kGridBlock) void k_grid_tile_offsets(const StepArgs a)
 {
     for (uint32_t i = blockIdx.x * kGridBlock + threadIdx.x; i < a.n_grid; i += gridDim.x * kGridBlock) {
-        const GridCell& gc = a.gcell[i];
+        GridCell& gc = a.gcell[i];
         uint32_t run = 0;
         for (uint32_t t = 0; t < gc.ntiles; ++t) {
             const uint32_t v = a.gtilesum[gc.tile0 + t];
@@ -923,6 +801,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_tile_offsets(const StepArgs
             run += v;
         }
         a.scr_cnt[a.off_begin[gc.cell] + gc.nb] = run;
+        gc.live = run;
         const unsigned long long pairs = run >> 1;
         if constexpr (BATCHED) {
             if (pairs) atomicAdd(&a.inst[a.cell_inst[gc.cell]].pair_tests, pairs);
@@ -961,49 +840,91 @@ static __global__ __launch_bounds__(kGridBlock) void k_grid_tile_scan(const Step
     }
 }
 
-template <bool BATCHED>
-__global__ __launch_bounds__(kGridBlock) void k_grid_scatter(const StepArgs a)
+// Place the M entries of src into dst (LDS or the bucket's scr_tmp range) by
+// sub-bucket, then rank each within its sub-bucket and write its slot to pos.
+// On entry s_sub holds the exclusive starts of the sub-buckets; placement
+// advances each to its end, so sub-bucket b spans [end(b-1), end(b)).
+template <typename SubOf>
+__device__ __forceinline__ void grid_place_rank(const uint64_t* __restrict__ src, uint64_t* dst,
+                                                uint32_t M, uint32_t* s_sub, SubOf sub_of,
+                                                uint32_t* __restrict__ pos)
 {
-    const uint2 ch = a.gchunk[blockIdx.x];
-    const GridCell& gc = a.gcell[ch.x];
-    const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
-    const uint32_t end = min(ch.y + kGridChunk, j.n_slots);
-    for (uint32_t s = ch.y + threadIdx.x; s < end; s += kGridBlock) {
-        if (a.xi[j.off + s] != 0) {
-            const uint64_t t = a.scr_tmp[j.off + s];
-            const uint32_t key = static_cast<uint32_t>(t >> 32);
-            const uint32_t p = a.scr_cnt[j.off + bucket_of(key, gc.lg)] + static_cast<uint32_t>(t);
-            a.scr_kv[j.off + p] = (static_cast<uint64_t>(key) << 32) | s;
-        }
+    for (uint32_t i = threadIdx.x; i < M; i += kGridBlock) {
+        const uint64_t v = src[i];
+        dst[atomicAdd(&s_sub[sub_of(v)], 1u)] = v;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < M; i += kGridBlock) {
+        const uint64_t v = dst[i];
+        const uint32_t b = sub_of(v);
+        const uint32_t e0 = b ? s_sub[b - 1] : 0u, e1 = s_sub[b];
+        uint32_t rank = 0;
+        for (uint32_t e = e0; e < e1; ++e) rank += dst[e] < v ? 1u : 0u;
+        pos[e0 + rank] = static_cast<uint32_t>(v);
     }
 }
 
-template <bool BATCHED>
-__global__ __launch_bounds__(kGridBlock) void k_grid_rank(const StepArgs a)
+// One workgroup per digit bucket: exact order of its (key, slot) words.
+static __global__ __launch_bounds__(kGridBlock) void k_grid_bucket_sort(const StepArgs a)
 {
-    const uint2 ch = a.gchunk[blockIdx.x];
-    const GridCell& gc = a.gcell[ch.x];
-    const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
-    const uint32_t end = min(ch.y + kGridChunk, j.n_slots);
-    for (uint32_t s = ch.y + threadIdx.x; s < end; s += kGridBlock) {
-        if (a.xi[j.off + s] != 0) {
-            const uint32_t key = static_cast<uint32_t>(a.scr_tmp[j.off + s] >> 32);
-            const uint32_t b = bucket_of(key, gc.lg);
-            const uint32_t lo = a.scr_cnt[j.off + b], hi = a.scr_cnt[j.off + b + 1];
-            const uint64_t me = (static_cast<uint64_t>(key) << 32) | s;
-            uint32_t rank = 0;
-            for (uint32_t e = lo; e < hi; ++e) rank += (a.scr_kv[j.off + e] < me) ? 1u : 0u;
-            a.scr_pos[j.off + lo + rank] = s;
-        }
+    __shared__ uint32_t s_sub[1u << kGridSubLg];
+    __shared__ uint64_t s_kv[kGridSortCap];
+    __shared__ uint32_t s_red[kGridBlock / kWave];
+    const uint2 gb = a.gbucket[blockIdx.x];
+    const GridCell& gc = a.gcell[gb.x];
+    const uint32_t off = a.off_begin[gc.cell];
+    const uint32_t lo = a.scr_cnt[off + gb.y * gc.ncol];
+    const uint32_t M = a.scr_cnt[off + (gb.y + 1) * gc.ncol] - lo;   // entry nb is the sentinel
+    const uint64_t* src = a.scr_kv + off + lo;
+    uint32_t* pos = a.scr_pos + off + lo;
+    if (M < 2) {
+        if (M == 1 && threadIdx.x == 0) pos[0] = static_cast<uint32_t>(src[0]);
+        return;
     }
+    const uint32_t cb = gc.cb;
+    const uint32_t sb = min(ceil_log2(M) - 1u, kGridSubLg);
+    const uint32_t S = 1u << sb;
+    const auto sub_of = [cb, sb](uint64_t v) {
+        return bucket_of(static_cast<uint32_t>(v >> 32) << cb, sb);
+    };
+    for (uint32_t b = threadIdx.x; b < S; b += kGridBlock) s_sub[b] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < M; i += kGridBlock) atomicAdd(&s_sub[sub_of(src[i])], 1u);
+    __syncthreads();
+    // exclusive scan of s_sub[0, S): thread t owns a run of `per` entries
+    {
+        constexpr int W = kGridBlock / kWave;
+        const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+        const uint32_t per = (S + kGridBlock - 1) / kGridBlock;
+        const uint32_t b0 = threadIdx.x * per;
+        const uint32_t b1 = min(b0 + per, S);
+        uint32_t run = 0;
+        for (uint32_t b = b0; b < b1; ++b) run += s_sub[b];
+        const uint32_t incl = wave_inclusive_sum(run, lane);
+        if (lane == kWave - 1) s_red[wv] = incl;
+        __syncthreads();
+        uint32_t before = incl - run;
+#pragma unroll
+        for (int w = 0; w < W; ++w) before += static_cast<uint32_t>(w) < wv ? s_red[w] : 0u;
+        for (uint32_t b = b0; b < b1; ++b) {
+            const uint32_t c = s_sub[b];
+            s_sub[b] = before;
+            before += c;
+        }
+        __syncthreads();
+    }
+    if (M <= kGridSortCap) grid_place_rank(src, s_kv, M, s_sub, sub_of, pos);
+    else grid_place_rank(src, a.scr_tmp + off + lo, M, s_sub, sub_of, pos);
 }
 
-// pair tests: each thread takes the two pairs of one uniform call
+// Pair tests: each thread takes the two pairs of one uniform call.  The pair
+// chunks of a cell go to one XCD (consecutive list entries, XCD-contiguous
+// block mapping), so the random reads of its xi and r share that XCD's L2.
 template <bool BATCHED, bool PERM>
 __global__ __launch_bounds__(kGridBlock) void k_grid_pairs(const StepArgs a)
 {
     __shared__ uint32_t s_red[kGridBlock / kWave];
-    const uint2 ch = a.gpchunk[blockIdx.x];
+    const uint2 ch = a.gpchunk[xcd_contiguous_block(blockIdx.x, gridDim.x)];
     const GridCell& gc = a.gcell[ch.x];
     const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
     const uint32_t n = gc.live;

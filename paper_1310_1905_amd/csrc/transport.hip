@@ -555,7 +555,6 @@ sdm_status refresh_plan(sdm_ctx* x)
                 SDM_TRY(upload_grid(st, empty, &x->grid));
                 x->n_groups = info[1];
                 x->n_wave_cells = nc;
-                x->n_block = 0;
                 x->sizes_stale = true;
                 return SDM_OK;
             }

@@ -34,7 +34,7 @@ class KernelParams(ctypes.Structure):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("group_slots", _u32), ("groups_per_wave", _u32), ("waves_per_block", _u32),
-                ("block_threads", _u32), ("xcd_remap", _u32)]
+                ("xcd_remap", _u32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -332,7 +332,7 @@ class Context:
         return order[: self.n_sd], nlive[: self.n_cells]
 
     def plan(self):
-        """(wave-tier groups, cells in them, workgroup-tier cells)."""
+        """(wave-tier groups, cells in them, grid-tier cells)."""
         g, w, b = _u32(), _u32(), _u32()
         _check(lib().sdm_get_plan(self._ctx, ctypes.byref(g), ctypes.byref(w), ctypes.byref(b)),
                "sdm_get_plan")

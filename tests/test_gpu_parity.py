@@ -5,8 +5,9 @@ radii within 1e-12 relative -- and since both sides round the cube root
 correctly and evaluate eq. (P_ij) in the same order without contraction, the
 radii are checked bit-exact as well.
 
-Cases: ragged cells of both kernel tiers (wave per cell up to 256 storage slots,
-workgroup per cell above), empty / single-SD / dead-SD cells, both collection
+Cases: ragged cells of both kernel tiers (wavefront groups up to 256 or 512
+storage slots, the grid tier above, including a cell of 2^23 slots whose digit
+buckets overflow LDS), empty / single-SD / dead-SD cells, both collection
 kernels, many steps; the 2D domain (75 x 75 x 64 SDs, 600 steps); the Golovin box
 (8192 SDs in one cell); the large domain at reduced size in full and at full size
 (1024 x 1024 cells, ~134M SDs, in the launch configuration the benchmark times) on
@@ -72,7 +73,7 @@ def test_permutation_bit_exact(sdm_mod, oracle_mod, max_per_cell):
     dict(group_slots=256, groups_per_wave=1, waves_per_block=1, xcd_remap=0),
     dict(group_slots=256, groups_per_wave=3, waves_per_block=4, xcd_remap=1),
     dict(group_slots=512, groups_per_wave=1, waves_per_block=2, xcd_remap=0),
-    dict(group_slots=512, groups_per_wave=8, waves_per_block=4, xcd_remap=1, block_threads=1024),
+    dict(group_slots=512, groups_per_wave=8, waves_per_block=4, xcd_remap=1),
 ])
 def test_launch_shapes_give_identical_results(sdm_mod, oracle_mod, shape):
     pop = synth.tiny_cells(seed=55, n_cells=700, max_per_cell=600, xi_max=40)
@@ -96,13 +97,13 @@ def test_many_cells_per_group(sdm_mod, oracle_mod):
     pop = synth.tiny_cells(seed=8, n_cells=3000, max_per_cell=4, xi_max=9, dead_fraction=0.2)
     ctx, ref = _run_pair(sdm_mod, oracle_mod, pop, 8, 5.0, "golovin", dV_scale=1e-9)
     _assert_same(ctx, ref, "tiny cells")
-    groups, wave_cells, block_cells = ctx.plan()
-    assert wave_cells == pop.n_cells and block_cells == 0 and groups <= pop.n_cells // 64 + 60
+    groups, wave_cells, grid_cells = ctx.plan()
+    assert wave_cells == pop.n_cells and grid_cells == 0 and groups <= pop.n_cells // 64 + 60
 
 
 @pytest.mark.parametrize("kernel", ["geometric", "golovin"])
 def test_grid_tier_cells(sdm_mod, oracle_mod, kernel):
-    """Cells above 16384 storage slots run spread over many workgroups."""
+    """Cells of up to 60000 storage slots, spread over many workgroups."""
     pop = synth.tiny_cells(seed=91, n_cells=6, max_per_cell=60000, xi_max=30, dead_fraction=0.2)
     sizes = np.bincount(pop.cell, minlength=pop.n_cells)
     assert (sizes > 16384).sum() >= 3
@@ -116,6 +117,36 @@ def test_grid_tier_cells(sdm_mod, oracle_mod, kernel):
         exp = oracle_mod.cell_order(ref.xi[off[c]:off[c + 1]], 17, c, 3)
         assert nlive[c] == exp.size
         assert np.array_equal(order[off[c]:off[c] + exp.size], exp), c
+
+
+def test_grid_tier_huge_cell(sdm_mod, oracle_mod):
+    """One cell of 2^23 + 1000 storage slots next to a 700-slot one: its 4096
+    digit buckets hold about 2048 live entries each, so buckets within and beyond
+    the LDS capacity of the bucket sort both occur; the pairing order and two
+    steps are bit-exact."""
+    g = np.random.default_rng(2323)
+    n_big = (1 << 23) + 1000
+    cell = np.concatenate([np.zeros(n_big, np.uint32), np.ones(700, np.uint32)])
+    n = cell.size
+    xi = g.integers(1, 31, n).astype(np.uint64)
+    xi[g.random(n) < 0.01] = 0
+    r = np.exp(g.uniform(np.log(5e-6), np.log(2e-3), n))
+    dV = np.array([1e3, 1e-3])
+    ctx = sdm_mod.Context(cell, xi, r, dV)
+    assert ctx.plan()[1:] == (0, 2)
+    ref = oracle_mod.SlotState(cell, xi, r, dV)
+    order, nlive = ctx.permutation(seed=99, step=5)
+    order, nlive = order.cpu().numpy(), nlive.cpu().numpy()
+    off = ref.offsets.astype(np.int64)
+    for c in range(2):
+        exp = oracle_mod.cell_order(ref.xi[off[c]:off[c + 1]], 99, c, 5)
+        assert nlive[c] == exp.size
+        assert np.array_equal(order[off[c]:off[c] + exp.size], exp), c
+    for t in range(2):
+        ctx.step(1.0, "geometric", 7, t)
+        ref.step(1.0, oracle_mod.GEOMETRIC, 7, t)
+    _assert_same(ctx, ref, "huge grid cell")
+    assert ref.stats[1] > 0
 
 
 def test_empty_and_degenerate_inputs(sdm_mod, oracle_mod):

@@ -47,7 +47,7 @@ def _recycle_ref(oracle_mod, ref):
     return total
 
 
-CASES = [(60, 200), (600, 120), (40000, 3)]   # wave, workgroup and grid tiers
+CASES = [(60, 200), (600, 120), (40000, 3)]   # wave tier; one- and many-chunk grid cells
 
 
 @pytest.mark.parametrize("max_per_cell,n_cells", CASES)
