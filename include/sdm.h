@@ -252,7 +252,7 @@ sdm_status sdm_coalesce_adaptive(sdm_ctx *ctx, double dt, double p_limit, uint32
 /* ------------------------------------------------------------------------ */
 
 /* Bytes of the caller-owned device workspace sdm_transport_attach needs
- * (about 72 B per super-droplet and 16 B per cell: positions, re-sort targets
+ * (about 64 B per super-droplet and 25 B per cell: positions, re-sort targets
  * of positions, xi, r and the input index, and the re-sort of the particles
  * that change cell). */
 size_t sdm_transport_workspace_bytes(uint64_t n_sd, uint32_t n_cells);
@@ -263,9 +263,9 @@ size_t sdm_transport_workspace_bytes(uint64_t n_sd, uint32_t n_cells);
  * (clamped to the grid), and the storage is re-sorted by those cells at once
  * (stable in the present storage order), which also rebuilds the launch plan.
  * The workspace (256-byte aligned) must stay allocated while the context lives.
- * Synchronises.  Errors: SDM_EINVAL (grid, spacing, NULL or out-of-domain
- * positions, workspace), SDM_ENOMEM (workspace too small), SDM_ESTATE (already
- * attached). */
+ * Synchronises.  Errors: SDM_EINVAL (grid, more than 2^31 - 1 cells, spacing,
+ * NULL or out-of-domain positions, workspace), SDM_ENOMEM (workspace too
+ * small), SDM_ESTATE (already attached). */
 sdm_status sdm_transport_attach(sdm_ctx *ctx, void *workspace, size_t ws_bytes, uint32_t nx,
                                 uint32_t nz, double dx, double dz, const double *x_in,
                                 const double *z_in);

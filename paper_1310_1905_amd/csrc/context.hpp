@@ -21,12 +21,12 @@ struct TransportState {
     uint64_t* xi_alt = nullptr;
     double* r_alt = nullptr;
     uint32_t* id_alt = nullptr;
-    uint32_t* cell = nullptr;   // new cell of every slot
+    uint32_t* cell = nullptr;   // new cell of every slot, top bit set if it changed
     // re-sort of the particles that changed cell
-    uint32_t* moved = nullptr;      // 1 if the slot's particle changed cell (n + 1 entries)
-    uint32_t* mprefix = nullptr;    // exclusive prefix of moved (n + 1)
-    uint32_t* mk = nullptr;         // movers: new cell, in old-slot order
+    uint32_t* tcnt = nullptr;       // movers per 256-slot tile, then their exclusive prefix
+    uint32_t* mk = nullptr;         // movers: new cell, in old-slot order (then the inverse order)
     uint32_t* mv = nullptr;         // movers: old slot
+    uint32_t* mlo = nullptr;        // per cell: movers with an old slot below the cell
     uint32_t* off_alt = nullptr;    // new slot offsets (swapped with the live offsets)
     uint32_t* inc_off = nullptr;    // offsets of the incoming movers per new cell
     uint32_t* in_low = nullptr;     // incoming movers from lower cells, per cell

@@ -78,49 +78,121 @@ __global__ void k_cells_of(uint64_t n, const double* x, const double* z, uint32_
         cell[s] = column_of(x[s], dx, nx) + nx * column_of(z[s], dz, nz);
 }
 
-// One transport step of every super-droplet (storage order).
-__global__ void k_transport(uint64_t n, uint32_t nx, uint32_t nz, double dx, double dz,
-                            const double* __restrict__ cx, const double* __restrict__ cz,
-                            double dt, int sediment, KernelParams kp, double Lx, double Lz,
-                            double* __restrict__ x, double* __restrict__ z,
-                            uint64_t* __restrict__ xi, const double* __restrict__ r,
-                            uint32_t* __restrict__ cell, uint32_t* __restrict__ moved)
+// Slots are handled in tiles of kTileSlots consecutive slots, one workgroup of
+// kTileThreads threads per tile (grid-stride over tiles), each thread taking
+// kTileK slots of the tile (slot k * kTileThreads + thread), so that per-tile
+// mover counts and in-tile prefixes need no per-slot prefix array and every
+// thread has kTileK independent loads in flight.
+constexpr uint32_t kTileThreads = 256;
+constexpr uint32_t kTileK = 4;
+constexpr uint32_t kTileSlots = kTileThreads * kTileK;
+constexpr uint32_t kTileWaves = kTileThreads / 64u;
+constexpr uint32_t kMovedBit = 0x80000000u;   // in the cell word: the particle changed cell
+
+// Exclusive prefix of flag[k] over the tile in slot order, and in *total its sum.
+// Every thread of the workgroup must call it.
+__device__ __forceinline__ void tile_prefix(const bool (&flag)[kTileK], uint32_t (&pre)[kTileK],
+                                            uint32_t* s_w, uint32_t* total)
 {
-    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
-         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        const double x0 = x[s], z0 = z[s];
-        const uint32_t i = column_of(x0, dx, nx);
-        const uint32_t k = column_of(z0, dz, nz);
-        double xn = x0, zn = z0;
-        if (cx) {
-            const double l = cx[static_cast<uint64_t>(k) * nx + i];
-            const double rr = cx[static_cast<uint64_t>(k) * nx + (i + 1u == nx ? 0u : i + 1u)];
-            xn = advect_1d(x0, dx, i, l, rr);
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const unsigned long long lanes_lt = (1ull << lane) - 1ull;
+    uint32_t in_wave[kTileK];
+#pragma unroll
+    for (uint32_t k = 0; k < kTileK; ++k) {
+        const unsigned long long b = __ballot(flag[k]);
+        in_wave[k] = static_cast<uint32_t>(__popcll(b & lanes_lt));
+        if (lane == 0) s_w[k * kTileWaves + wv] = static_cast<uint32_t>(__popcll(b));
+    }
+    __syncthreads();
+    uint32_t run = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kTileK; ++k) {
+        uint32_t before = 0, sub = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < kTileWaves; ++w) {
+            const uint32_t v = s_w[k * kTileWaves + w];
+            before += w < wv ? v : 0u;
+            sub += v;
         }
-        if (cz) {
-            const double b = cz[static_cast<uint64_t>(k) * nx + i];
-            const double t = cz[static_cast<uint64_t>(k + 1u) * nx + i];
-            zn = advect_1d(z0, dz, k, b, t);
+        pre[k] = run + before + in_wave[k];
+        run += sub;
+    }
+    __syncthreads();
+    *total = run;
+}
+
+__device__ __forceinline__ uint64_t tile_slot(uint64_t t, uint32_t k)
+{
+    return t * kTileSlots + k * kTileThreads + threadIdx.x;
+}
+
+// One transport step of every super-droplet (storage order).  cellm[s] gets the
+// new cell, with kMovedBit set if it differs from the old one; tcnt[t] the
+// number of such movers in tile t.
+__global__ __launch_bounds__(kTileThreads) void k_transport(
+    uint64_t n, uint32_t nx, uint32_t nz, double dx, double dz, const double* __restrict__ cx,
+    const double* __restrict__ cz, double dt, int sediment, KernelParams kp, double Lx, double Lz,
+    double* __restrict__ x, double* __restrict__ z, uint64_t* __restrict__ xi,
+    const double* __restrict__ r, uint32_t* __restrict__ cellm, uint32_t* __restrict__ tcnt)
+{
+    __shared__ uint32_t s_w[kTileK * kTileWaves];
+    const uint64_t ntiles = (n + kTileSlots - 1) / kTileSlots;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        double x0[kTileK], z0[kTileK], rv[kTileK];
+#pragma unroll
+        for (uint32_t k = 0; k < kTileK; ++k) {
+            const uint64_t s = tile_slot(t, k);
+            x0[k] = 0.0;
+            z0[k] = 0.0;
+            rv[k] = 0.0;
+            if (s < n) {
+                x0[k] = x[s];
+                z0[k] = z[s];
+                if (sediment) rv[k] = r[s];
+            }
         }
-        if (sediment) zn = zn - terminal_velocity(kp, r[s]) * dt;
-        if (xn < 0.0) {
-            xn = xn + Lx;
-            if (xn >= Lx) xn = 0.0;
-        } else if (xn >= Lx) {
-            xn = xn - Lx;
+        bool moved[kTileK];
+#pragma unroll
+        for (uint32_t k = 0; k < kTileK; ++k) {
+            const uint64_t s = tile_slot(t, k);
+            moved[k] = false;
+            if (s >= n) continue;
+            const uint32_t i = column_of(x0[k], dx, nx);
+            const uint32_t kk = column_of(z0[k], dz, nz);
+            double xn = x0[k], zn = z0[k];
+            if (cx) {
+                const double l = cx[static_cast<uint64_t>(kk) * nx + i];
+                const double rr = cx[static_cast<uint64_t>(kk) * nx + (i + 1u == nx ? 0u : i + 1u)];
+                xn = advect_1d(x0[k], dx, i, l, rr);
+            }
+            if (cz) {
+                const double b = cz[static_cast<uint64_t>(kk) * nx + i];
+                const double tp = cz[static_cast<uint64_t>(kk + 1u) * nx + i];
+                zn = advect_1d(z0[k], dz, kk, b, tp);
+            }
+            if (sediment) zn = zn - terminal_velocity(kp, rv[k]) * dt;
+            if (xn < 0.0) {
+                xn = xn + Lx;
+                if (xn >= Lx) xn = 0.0;
+            } else if (xn >= Lx) {
+                xn = xn - Lx;
+            }
+            if (zn < 0.0) {
+                xi[s] = 0;
+                zn = 0.0;
+            } else if (zn >= Lz) {
+                xi[s] = 0;
+                zn = static_cast<double>(nz - 1u) * dz;
+            }
+            x[s] = xn;
+            z[s] = zn;
+            const uint32_t c_new = column_of(xn, dx, nx) + nx * column_of(zn, dz, nz);
+            moved[k] = c_new != i + nx * kk;
+            cellm[s] = c_new | (moved[k] ? kMovedBit : 0u);
         }
-        if (zn < 0.0) {
-            xi[s] = 0;
-            zn = 0.0;
-        } else if (zn >= Lz) {
-            xi[s] = 0;
-            zn = static_cast<double>(nz - 1u) * dz;
-        }
-        x[s] = xn;
-        z[s] = zn;
-        const uint32_t c_new = column_of(xn, dx, nx) + nx * column_of(zn, dz, nz);
-        cell[s] = c_new;
-        moved[s] = c_new != i + nx * k ? 1u : 0u;
+        uint32_t pre[kTileK], tot = 0;
+        tile_prefix(moved, pre, s_w, &tot);
+        if (threadIdx.x == 0) tcnt[t] = tot;
     }
 }
 
@@ -129,31 +201,60 @@ __global__ void k_transport(uint64_t n, uint32_t nx, uint32_t nz, double dx, dou
 // ("movers") are sorted; the others keep their relative order.  In the stable
 // order by (new cell, old slot), cell c holds first the movers that come from
 // lower cells (old slot below c's old range), then its stayers, then the movers
-// from higher cells, each in old-slot order.  mprefix is the exclusive prefix
-// count of movers over the old slots.
+// from higher cells, each in old-slot order.  tpre is the exclusive prefix of
+// the per-tile mover counts; the movers before slot s are tpre[tile] plus the
+// movers before s in its tile.
 // ---------------------------------------------------------------------------
-__global__ void k_compact_movers(uint64_t n, const uint32_t* __restrict__ moved,
-                                 const uint32_t* __restrict__ mprefix,
-                                 const uint32_t* __restrict__ cell, uint32_t* __restrict__ mk,
-                                 uint32_t* __restrict__ mv)
+__global__ __launch_bounds__(kTileThreads) void k_compact_movers(uint64_t n,
+                                                                  const uint32_t* __restrict__ cellm,
+                                                                  const uint32_t* __restrict__ tpre,
+                                                                  uint32_t* __restrict__ mk,
+                                                                  uint32_t* __restrict__ mv)
 {
-    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
-         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        if (moved[s]) {
-            const uint32_t m = mprefix[s];
-            mk[m] = cell[s];
-            mv[m] = static_cast<uint32_t>(s);
+    __shared__ uint32_t s_w[kTileK * kTileWaves];
+    const uint64_t ntiles = (n + kTileSlots - 1) / kTileSlots;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t base = tpre[t];
+        uint32_t v[kTileK];
+        bool moved[kTileK];
+#pragma unroll
+        for (uint32_t k = 0; k < kTileK; ++k) {
+            const uint64_t s = tile_slot(t, k);
+            v[k] = s < n ? cellm[s] : 0u;
+            moved[k] = (v[k] & kMovedBit) != 0;
+        }
+        uint32_t pre[kTileK], tot = 0;
+        tile_prefix(moved, pre, s_w, &tot);
+#pragma unroll
+        for (uint32_t k = 0; k < kTileK; ++k) {
+            if (!moved[k]) continue;
+            const uint32_t m = base + pre[k];
+            mk[m] = v[k] & ~kMovedBit;
+            mv[m] = static_cast<uint32_t>(tile_slot(t, k));
         }
     }
 }
 
-// New per-cell counts (old - outgoing + incoming) and, per cell, the number of
-// incoming movers from lower cells.  count has n_cells + 1 entries (last 0).
-__global__ void k_new_counts(uint32_t n_cells, const uint32_t* __restrict__ old_off,
-                             const uint32_t* __restrict__ mprefix,
+// first index in mv[0, m) (ascending) whose value is >= key
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ mv, uint32_t lo,
+                                                    uint32_t hi, uint32_t key)
+{
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (mv[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// New per-cell counts (old - outgoing + incoming), the incoming movers from lower
+// cells, and mlo[c] = movers with an old slot below the cell's old range (the
+// compacted movers are in old-slot order).  count has n_cells + 1 entries (last 0).
+__global__ void k_new_counts(uint32_t n_cells, const uint32_t* __restrict__ old_off, uint32_t m_tot,
                              const uint32_t* __restrict__ inc_off,
                              const uint32_t* __restrict__ order, const uint32_t* __restrict__ mv,
-                             uint32_t* __restrict__ count, uint32_t* __restrict__ in_low)
+                             uint32_t* __restrict__ count, uint32_t* __restrict__ in_low,
+                             uint32_t* __restrict__ mlo)
 {
     for (uint64_t c = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; c <= n_cells;
          c += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
@@ -162,81 +263,96 @@ __global__ void k_new_counts(uint32_t n_cells, const uint32_t* __restrict__ old_
             continue;
         }
         const uint32_t ob = old_off[c], oe = old_off[c + 1];
-        const uint32_t out = mprefix[oe] - mprefix[ob];
+        const uint32_t lo = lower_bound_u32(mv, 0, m_tot, ob);
+        const uint32_t out = lower_bound_u32(mv, lo, m_tot, oe) - lo;
+        mlo[c] = lo;
         const uint32_t ib = inc_off[c], ie = inc_off[c + 1];
         count[c] = (oe - ob) - out + (ie - ib);
         // incoming movers are in old-slot order: count those below the cell's old range
-        uint32_t lo = ib, hi = ie;
-        while (lo < hi) {
-            const uint32_t mid = lo + (hi - lo) / 2;
-            if (mv[order[mid]] < ob) lo = mid + 1;
-            else hi = mid;
+        uint32_t a = ib, b = ie;
+        while (a < b) {
+            const uint32_t mid = a + (b - a) / 2;
+            if (mv[order[mid]] < ob) a = mid + 1;
+            else b = mid;
         }
-        in_low[c] = lo - ib;
+        in_low[c] = a - ib;
     }
 }
 
-// Stayers: destination from their rank among the cell's stayers.
-__global__ void k_scatter_stayers(uint64_t n, const uint32_t* __restrict__ moved,
-                                  const uint32_t* __restrict__ mprefix,
-                                  const uint32_t* __restrict__ cell,
-                                  const uint32_t* __restrict__ old_off,
-                                  const uint32_t* __restrict__ new_off,
-                                  const uint32_t* __restrict__ in_low,
-                                  const uint64_t* __restrict__ xi, const double* __restrict__ r,
-                                  const uint32_t* __restrict__ id, const double* __restrict__ x,
-                                  const double* __restrict__ z, uint64_t* __restrict__ xi_o,
-                                  double* __restrict__ r_o, uint32_t* __restrict__ id_o,
-                                  double* __restrict__ x_o, double* __restrict__ z_o)
-{
-    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
-         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        // the slot's own loads first, all independent; the cell's offsets after
-        const uint32_t mv_s = moved[s], c = cell[s], mp = mprefix[s];
-        const uint64_t xv = xi[s];
-        const double rv = r[s], xs = x[s], zs = z[s];
-        const uint32_t iv = id[s];
-        if (mv_s) continue;
-        const uint32_t ob = old_off[c];
-        const uint64_t j = static_cast<uint64_t>(new_off[c]) + in_low[c] + (s - ob) -
-                           (mp - mprefix[ob]);
-        xi_o[j] = xv;
-        r_o[j] = rv;
-        id_o[j] = iv;
-        x_o[j] = xs;
-        z_o[j] = zs;
-    }
-}
-
-// Movers, in the order sorted by (new cell, old slot).
-__global__ void k_scatter_movers(uint32_t m_tot, const uint32_t* __restrict__ order,
-                                 const uint32_t* __restrict__ mk, const uint32_t* __restrict__ mv,
-                                 const uint32_t* __restrict__ inc_off,
-                                 const uint32_t* __restrict__ new_off,
-                                 const uint32_t* __restrict__ in_low,
-                                 const uint32_t* __restrict__ count,
-                                 const uint64_t* __restrict__ xi, const double* __restrict__ r,
-                                 const uint32_t* __restrict__ id, const double* __restrict__ x,
-                                 const double* __restrict__ z, uint64_t* __restrict__ xi_o,
-                                 double* __restrict__ r_o, uint32_t* __restrict__ id_o,
-                                 double* __restrict__ x_o, double* __restrict__ z_o)
+// inv[order[q]] = q: sorted position of every compacted mover
+__global__ void k_invert_order(uint32_t m_tot, const uint32_t* __restrict__ order,
+                               uint32_t* __restrict__ inv)
 {
     for (uint64_t q = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; q < m_tot;
-         q += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        const uint32_t e = order[q];
-        const uint32_t c = mk[e], s = mv[e];
-        const uint64_t xv = xi[s];
-        const double rv = r[s], xs = x[s], zs = z[s];
-        const uint32_t iv = id[s];
-        const uint32_t rank = static_cast<uint32_t>(q) - inc_off[c];
-        const uint32_t in_c = inc_off[c + 1] - inc_off[c];
-        const uint32_t stayers = count[c] - in_c;
-        const uint64_t j = static_cast<uint64_t>(new_off[c]) + rank + (rank >= in_low[c] ? stayers : 0u);
-        xi_o[j] = xv;
-        r_o[j] = rv;
-        id_o[j] = iv;
-        x_o[j] = xs;
-        z_o[j] = zs;
+         q += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        inv[order[q]] = static_cast<uint32_t>(q);
+}
+
+// Every particle to its new slot, reading the old storage in order.  A stayer
+// goes after the cell's incoming movers from lower cells, at its rank among the
+// cell's stayers; a mover (compacted index e, sorted position inv[e]) to its
+// rank among the new cell's incoming movers, after the stayers if it comes from
+// a higher cell.
+__global__ __launch_bounds__(kTileThreads) void k_scatter_resort(
+    uint64_t n, const uint32_t* __restrict__ cellm, const uint32_t* __restrict__ tpre,
+    const uint32_t* __restrict__ old_off, const uint32_t* __restrict__ new_off,
+    const uint32_t* __restrict__ in_low, const uint32_t* __restrict__ mlo,
+    const uint32_t* __restrict__ inv, const uint32_t* __restrict__ inc_off,
+    const uint32_t* __restrict__ count, const uint64_t* __restrict__ xi,
+    const double* __restrict__ r, const uint32_t* __restrict__ id, const double* __restrict__ x,
+    const double* __restrict__ z, uint64_t* __restrict__ xi_o, double* __restrict__ r_o,
+    uint32_t* __restrict__ id_o, double* __restrict__ x_o, double* __restrict__ z_o)
+{
+    __shared__ uint32_t s_w[kTileK * kTileWaves];
+    const uint64_t ntiles = (n + kTileSlots - 1) / kTileSlots;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t base = tpre[t];
+        // the slots' own loads first, all independent
+        uint32_t v[kTileK], iv[kTileK];
+        uint64_t xv[kTileK];
+        double rv[kTileK], xs[kTileK], zs[kTileK];
+        bool moved[kTileK];
+#pragma unroll
+        for (uint32_t k = 0; k < kTileK; ++k) {
+            const uint64_t s = tile_slot(t, k);
+            v[k] = 0u;
+            iv[k] = 0u;
+            xv[k] = 0u;
+            rv[k] = xs[k] = zs[k] = 0.0;
+            if (s < n) {
+                v[k] = cellm[s];
+                xv[k] = xi[s];
+                rv[k] = r[s];
+                xs[k] = x[s];
+                zs[k] = z[s];
+                iv[k] = id[s];
+            }
+            moved[k] = (v[k] & kMovedBit) != 0;
+        }
+        uint32_t pre[kTileK], tot = 0;
+        tile_prefix(moved, pre, s_w, &tot);
+#pragma unroll
+        for (uint32_t k = 0; k < kTileK; ++k) {
+            const uint64_t s = tile_slot(t, k);
+            if (s >= n) continue;
+            const uint32_t mp = base + pre[k];   // movers before s
+            const uint32_t c = v[k] & ~kMovedBit;
+            uint64_t j;
+            if (!moved[k]) {
+                j = static_cast<uint64_t>(new_off[c]) + in_low[c] +
+                    (static_cast<uint32_t>(s) - old_off[c]) - (mp - mlo[c]);
+            } else {
+                const uint32_t ib = inc_off[c];
+                const uint32_t rank = inv[mp] - ib;
+                const uint32_t stayers = count[c] - (inc_off[c + 1] - ib);
+                j = static_cast<uint64_t>(new_off[c]) + rank + (rank >= in_low[c] ? stayers : 0u);
+            }
+            xi_o[j] = xv[k];
+            r_o[j] = rv[k];
+            id_o[j] = iv[k];
+            x_o[j] = xs[k];
+            z_o[j] = zs[k];
+        }
     }
 }
 
@@ -391,7 +507,7 @@ __global__ void k_plan_check(uint32_t n_groups, uint32_t nc, const uint32_t* __r
 struct TransportLayout {
     double *x, *z, *x_alt, *z_alt, *r_alt;
     uint64_t* xi_alt;
-    uint32_t *id_alt, *cell, *moved, *mprefix, *mk, *mv;
+    uint32_t *id_alt, *cell, *tcnt, *mk, *mv, *mlo;
     uint32_t *off_alt, *inc_off, *in_low, *count, *tile_sums;
     uint8_t *jump, *exits, *entries;
     uint32_t *start, *plan_info;
@@ -410,10 +526,10 @@ TransportLayout transport_layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t
     L.r_alt = cv.take<double>(n);
     L.id_alt = cv.take<uint32_t>(n);
     L.cell = cv.take<uint32_t>(n);
-    L.moved = cv.take<uint32_t>(n + 1);
-    L.mprefix = cv.take<uint32_t>(n + 1);
+    L.tcnt = cv.take<uint32_t>((n + kTileSlots - 1) / kTileSlots + 1);
     L.mk = cv.take<uint32_t>(n);
     L.mv = cv.take<uint32_t>(n);
+    L.mlo = cv.take<uint32_t>(uint64_t(nc) + 1);
     L.off_alt = cv.take<uint32_t>(uint64_t(nc) + 1);
     L.inc_off = cv.take<uint32_t>(uint64_t(nc) + 1);
     L.in_low = cv.take<uint32_t>(nc);
@@ -481,27 +597,32 @@ sdm_status resort_moved(sdm_ctx* x)
     const uint64_t n = x->n_sd;
     const uint32_t nc = x->n_cells;
     hipStream_t st = x->stream;
-    SDM_TRY(scan_exclusive(st, T.moved, T.mprefix, n + 1, T.tile_sums));
+    const uint64_t ntiles = (n + kTileSlots - 1) / kTileSlots;
+    const dim3 tile_grid(static_cast<uint32_t>(ntiles < 8192u ? ntiles : 8192u));
+    const dim3 tile_block(kTileThreads);
+    // tile counts -> exclusive tile prefix; the entry past the last tile ends in the total
+    SDM_TRY(scan_exclusive(st, T.tcnt, T.tcnt, ntiles + 1, T.tile_sums));
     uint32_t m_tot = 0;
-    SDM_HIP(hipMemcpyAsync(&m_tot, T.mprefix + n, sizeof(m_tot), hipMemcpyDeviceToHost, st));
+    SDM_HIP(hipMemcpyAsync(&m_tot, T.tcnt + ntiles, sizeof(m_tot), hipMemcpyDeviceToHost, st));
     SDM_HIP(hipStreamSynchronize(st));
     if (m_tot == 0) return SDM_OK;   // nobody changed cell: storage, offsets and plan stay
-    hipLaunchKernelGGL(k_compact_movers, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, T.moved,
-                       T.mprefix, T.cell, T.mk, T.mv);
+    hipLaunchKernelGGL(k_compact_movers, tile_grid, tile_block, 0, st, n, T.cell, T.tcnt,
+                       T.mk, T.mv);
     SDM_LAUNCHED();
     const uint32_t* order = nullptr;
     SDM_TRY(radix_sort_by_cell(st, m_tot, T.mk, nc, x->sort, T.inc_off, &order));
     hipLaunchKernelGGL(k_new_counts, dim3(grid_for(uint64_t(nc) + 1, 256, 8192)), dim3(256), 0, st,
-                       nc, x->offsets, T.mprefix, T.inc_off, order, T.mv, T.count, T.in_low);
+                       nc, x->offsets, m_tot, T.inc_off, order, T.mv, T.count, T.in_low, T.mlo);
     SDM_LAUNCHED();
     SDM_TRY(scan_exclusive(st, T.count, T.off_alt, uint64_t(nc) + 1, T.tile_sums));
-    hipLaunchKernelGGL(k_scatter_stayers, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n,
-                       T.moved, T.mprefix, T.cell, x->offsets, T.off_alt, T.in_low, x->xi, x->r,
-                       x->id, T.x, T.z, T.xi_alt, T.r_alt, T.id_alt, T.x_alt, T.z_alt);
+    // the sort read its keys from mk: that array now takes the inverse order
+    uint32_t* inv = T.mk;
+    hipLaunchKernelGGL(k_invert_order, dim3(grid_for(m_tot, 256, 8192)), dim3(256), 0, st, m_tot,
+                       order, inv);
     SDM_LAUNCHED();
-    hipLaunchKernelGGL(k_scatter_movers, dim3(grid_for(m_tot, 256, 8192)), dim3(256), 0, st, m_tot,
-                       order, T.mk, T.mv, T.inc_off, T.off_alt, T.in_low, T.count, x->xi, x->r,
-                       x->id, T.x, T.z, T.xi_alt, T.r_alt, T.id_alt, T.x_alt, T.z_alt);
+    hipLaunchKernelGGL(k_scatter_resort, tile_grid, tile_block, 0, st, n, T.cell, T.tcnt,
+                       x->offsets, T.off_alt, T.in_low, T.mlo, inv, T.inc_off, T.count, x->xi,
+                       x->r, x->id, T.x, T.z, T.xi_alt, T.r_alt, T.id_alt, T.x_alt, T.z_alt);
     SDM_LAUNCHED();
     swap_state(x);
     std::swap(x->offsets, T.off_alt);
@@ -600,6 +721,10 @@ extern "C" sdm_status sdm_transport_attach(sdm_ctx* x, void* workspace, size_t w
         set_error("the grid (%u x %u) must have exactly n_cells = %u cells", nx, nz, x->n_cells);
         return SDM_EINVAL;
     }
+    if (x->n_cells > ~kMovedBit) {
+        set_error("transport supports at most 2^31 - 1 cells");
+        return SDM_EINVAL;
+    }
     if (!(dx > 0.0) || !(dz > 0.0) || !std::isfinite(dx) || !std::isfinite(dz)) {
         set_error("dx and dz must be finite and > 0");
         return SDM_EINVAL;
@@ -644,10 +769,10 @@ extern "C" sdm_status sdm_transport_attach(sdm_ctx* x, void* workspace, size_t w
     T->r_alt = L.r_alt;
     T->id_alt = L.id_alt;
     T->cell = L.cell;
-    T->moved = L.moved;
-    T->mprefix = L.mprefix;
+    T->tcnt = L.tcnt;
     T->mk = L.mk;
     T->mv = L.mv;
+    T->mlo = L.mlo;
     T->off_alt = L.off_alt;
     T->inc_off = L.inc_off;
     T->in_low = L.in_low;
@@ -659,10 +784,6 @@ extern "C" sdm_status sdm_transport_attach(sdm_ctx* x, void* workspace, size_t w
     T->start = L.start;
     T->plan_info = L.plan_info;
     x->transport = std::move(T);
-    // the flag past the last slot stays 0, so the prefix over n + 1 flags ends in the total
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n + 1, 256, 8192)), dim3(256), 0, x->stream,
-                       L.moved, n + 1, 0u);
-    SDM_LAUNCHED();
     if (n > 0) {
         hipLaunchKernelGGL(k_cells_of, dim3(grid_for(n, 256, 8192)), dim3(256), 0, x->stream, n,
                            L.x, L.z, nx, nz, dx, dz, L.cell);
@@ -694,10 +815,11 @@ extern "C" sdm_status sdm_transport_step(sdm_ctx* x, const double* cx, const dou
     }
     const uint64_t n = x->n_sd;
     if (n > 0) {
-        hipLaunchKernelGGL(k_transport, dim3(grid_for(n, 256, 8192)), dim3(256), 0, x->stream, n,
-                           T.nx, T.nz, T.dx, T.dz, cx, cz, dt, sediment ? 1 : 0, to_kp(x->params),
-                           static_cast<double>(T.nx) * T.dx, static_cast<double>(T.nz) * T.dz,
-                           T.x, T.z, x->xi, x->r, T.cell, T.moved);
+        const uint64_t ntiles = (n + kTileSlots - 1) / kTileSlots;
+        hipLaunchKernelGGL(k_transport, dim3(static_cast<uint32_t>(ntiles < 8192u ? ntiles : 8192u)),
+                           dim3(kTileThreads), 0, x->stream, n, T.nx, T.nz, T.dx, T.dz, cx, cz, dt,
+                           sediment ? 1 : 0, to_kp(x->params), static_cast<double>(T.nx) * T.dx,
+                           static_cast<double>(T.nz) * T.dz, T.x, T.z, x->xi, x->r, T.cell, T.tcnt);
         SDM_LAUNCHED();
     }
     return resort_moved(x);
