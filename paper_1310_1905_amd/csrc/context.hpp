@@ -36,6 +36,8 @@ struct TransportState {
     uint8_t* jump = nullptr;        // cells of the greedy group a cell would open
     uint8_t* exits = nullptr;       // chunk walk exits per entry
     uint8_t* entries = nullptr;     // chunk walk entries
+    uint8_t* super_exits = nullptr; // exits of runs of chunk tables, per entry
+    uint8_t* super_entries = nullptr;
     uint32_t* start = nullptr;      // group-start flags, then their prefix
     uint32_t* plan_info = nullptr;  // [0] large-cell flag, [1] plan check flag
 };

@@ -732,7 +732,9 @@ constexpr uint32_t kGridMaxDigits = 1u << kGridMaxDigitBits;
 constexpr uint32_t kGridTile = 4096;      // table entries per tile
 constexpr uint32_t kGridSortCap = 2048;   // larger buckets are ordered through scr_tmp
 constexpr uint32_t kGridSubLg = 10;       // at most 2^10 sub-buckets per bucket
-constexpr uint32_t kGridPairChunk = 2048; // pairs per pair chunk
+// pairs per pair chunk: small, so that the chunks running at once on one XCD
+// cover few cells and their xi and r stay in that XCD's L2
+constexpr uint32_t kGridPairChunk = 512;
 
 // Digit counts (PLACE = false) or placement (PLACE = true) of one slot chunk.
 // Placement starts each digit's cursor at the chunk's scanned table entry; the

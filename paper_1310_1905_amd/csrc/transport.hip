@@ -392,11 +392,14 @@ __global__ void k_positions_out(uint64_t n, const uint32_t* id, const double* x,
 // the next cell, and the group starts are the small cells on the walk from cell
 // 0.  Jumps are at most kGroupMaxCells long, so the walk is cut into chunks of
 // kPlanChunk cells: every chunk is walked from each of its first
-// kGroupMaxCells cells at once (one lane per entry, the jumps in LDS), the
-// chunk entries are chained by one thread, and the real walk of every chunk
-// then marks its group starts.
+// kGroupMaxCells cells at once (one lane per entry, the jumps in LDS), giving
+// a 64-entry exit table per chunk.  The tables are chained in two levels:
+// each run of kPlanSuper chunks composes its tables into one, one thread
+// chains those, and each run then hands the entries down to its chunks.  The
+// real walk of every chunk then marks its group starts.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kPlanChunk = 4096;
+constexpr uint32_t kPlanChunk = 1024;
+constexpr uint32_t kPlanSuper = 64;   // chunks per run of the chaining
 constexpr uint8_t kPlanBig = 0x80;
 
 // jump[c] = cells in the greedy group that cell c would open (1..64), or
@@ -440,37 +443,80 @@ __global__ __launch_bounds__(kGroupMaxCells) void k_plan_chunks(uint32_t nc,
         static_cast<uint8_t>(p - len);
 }
 
-__global__ void k_plan_stitch(uint32_t n_chunks, const uint8_t* __restrict__ exits,
-                              uint8_t* __restrict__ entries)
+// super_exits[S * 64 + e]: where the walk entering the first chunk of run S at
+// cell e leaves the run (offset into the chunk after it).
+__global__ __launch_bounds__(kGroupMaxCells) void k_plan_super(uint32_t n_chunks,
+                                                              const uint8_t* __restrict__ exits,
+                                                              uint8_t* __restrict__ super_exits)
+{
+    __shared__ uint8_t s_ex[kPlanSuper * kGroupMaxCells];
+    const uint32_t j0 = blockIdx.x * kPlanSuper;
+    const uint32_t nj = n_chunks - j0 < kPlanSuper ? n_chunks - j0 : kPlanSuper;
+    for (uint32_t i = threadIdx.x; i < nj * kGroupMaxCells; i += blockDim.x)
+        s_ex[i] = exits[static_cast<uint64_t>(j0) * kGroupMaxCells + i];
+    __syncthreads();
+    uint32_t e = threadIdx.x;
+    for (uint32_t j = 0; j < nj; ++j) e = s_ex[j * kGroupMaxCells + e];
+    super_exits[static_cast<uint64_t>(blockIdx.x) * kGroupMaxCells + threadIdx.x] =
+        static_cast<uint8_t>(e);
+}
+
+// one thread: the entry of every run (the walk starts at cell 0)
+__global__ void k_plan_stitch(uint32_t n_super, const uint8_t* __restrict__ super_exits,
+                              uint8_t* __restrict__ super_entries)
 {
     uint32_t e = 0;
-    for (uint32_t j = 0; j < n_chunks; ++j) {
-        entries[j] = static_cast<uint8_t>(e);
-        e = exits[static_cast<uint64_t>(j) * kGroupMaxCells + e];
+    for (uint32_t S = 0; S < n_super; ++S) {
+        super_entries[S] = static_cast<uint8_t>(e);
+        e = super_exits[static_cast<uint64_t>(S) * kGroupMaxCells + e];
     }
 }
 
-// start[c] = 1 for the group starts of chunk j (small cells on the walk), else 0.
+// the entry of every chunk of run S, from the run's entry
+__global__ __launch_bounds__(kGroupMaxCells) void k_plan_entries(
+    uint32_t n_chunks, const uint8_t* __restrict__ exits, const uint8_t* __restrict__ super_entries,
+    uint8_t* __restrict__ entries)
+{
+    __shared__ uint8_t s_ex[kPlanSuper * kGroupMaxCells];
+    const uint32_t j0 = blockIdx.x * kPlanSuper;
+    const uint32_t nj = n_chunks - j0 < kPlanSuper ? n_chunks - j0 : kPlanSuper;
+    for (uint32_t i = threadIdx.x; i < nj * kGroupMaxCells; i += blockDim.x)
+        s_ex[i] = exits[static_cast<uint64_t>(j0) * kGroupMaxCells + i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t e = super_entries[blockIdx.x];
+        for (uint32_t j = 0; j < nj; ++j) {
+            entries[j0 + j] = static_cast<uint8_t>(e);
+            e = s_ex[j * kGroupMaxCells + e];
+        }
+    }
+}
+
+// start[c] = 1 for the group starts of chunk j (small cells on the walk), else 0;
+// the walk marks in LDS, the flags are written out by the whole workgroup.
 __global__ __launch_bounds__(256) void k_plan_mark(uint32_t nc, const uint8_t* __restrict__ jump,
                                                    const uint8_t* __restrict__ entries,
                                                    uint32_t* __restrict__ start)
 {
     __shared__ uint8_t s_jump[kPlanChunk];
+    __shared__ uint8_t s_mark[kPlanChunk];
     const uint32_t c0 = blockIdx.x * kPlanChunk;
     const uint32_t len = nc - c0 < kPlanChunk ? nc - c0 : kPlanChunk;
     for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
         s_jump[i] = jump[c0 + i];
-        start[c0 + i] = 0;
+        s_mark[i] = 0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t p = entries[blockIdx.x];
         while (p < len) {
             const uint8_t j = s_jump[p];
-            if (!(j & kPlanBig)) start[c0 + p] = 1u;
+            if (!(j & kPlanBig)) s_mark[p] = 1;
             p += j & 0x7Fu;
         }
     }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) start[c0 + i] = s_mark[i];
 }
 
 __global__ void k_plan_emit(uint32_t nc, const uint32_t* __restrict__ prefix,
@@ -509,7 +555,7 @@ struct TransportLayout {
     uint64_t* xi_alt;
     uint32_t *id_alt, *cell, *tcnt, *mk, *mv, *mlo;
     uint32_t *off_alt, *inc_off, *in_low, *count, *tile_sums;
-    uint8_t *jump, *exits, *entries;
+    uint8_t *jump, *exits, *entries, *super_exits, *super_entries;
     uint32_t *start, *plan_info;
     size_t bytes;
 };
@@ -540,6 +586,9 @@ TransportLayout transport_layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t
     L.jump = cv.take<uint8_t>(uint64_t(nc) + 1);
     L.exits = cv.take<uint8_t>(chunks * kGroupMaxCells);
     L.entries = cv.take<uint8_t>(chunks);
+    const uint64_t supers = (chunks + kPlanSuper - 1) / kPlanSuper;
+    L.super_exits = cv.take<uint8_t>(supers * kGroupMaxCells);
+    L.super_entries = cv.take<uint8_t>(supers);
     L.start = cv.take<uint32_t>(uint64_t(nc) + 1);
     L.plan_info = cv.take<uint32_t>(64);
     L.bytes = cv.used();
@@ -647,7 +696,15 @@ sdm_status refresh_plan(sdm_ctx* x)
         hipLaunchKernelGGL(k_plan_chunks, dim3(chunks), dim3(kGroupMaxCells), 0, st, nc, T.jump,
                            T.exits);
         SDM_LAUNCHED();
-        hipLaunchKernelGGL(k_plan_stitch, dim3(1), dim3(1), 0, st, chunks, T.exits, T.entries);
+        const uint32_t supers = (chunks + kPlanSuper - 1) / kPlanSuper;
+        hipLaunchKernelGGL(k_plan_super, dim3(supers), dim3(kGroupMaxCells), 0, st, chunks, T.exits,
+                           T.super_exits);
+        SDM_LAUNCHED();
+        hipLaunchKernelGGL(k_plan_stitch, dim3(1), dim3(1), 0, st, supers, T.super_exits,
+                           T.super_entries);
+        SDM_LAUNCHED();
+        hipLaunchKernelGGL(k_plan_entries, dim3(supers), dim3(kGroupMaxCells), 0, st, chunks,
+                           T.exits, T.super_entries, T.entries);
         SDM_LAUNCHED();
         hipLaunchKernelGGL(k_plan_mark, dim3(chunks), dim3(256), 0, st, nc, T.jump, T.entries,
                            T.start);
@@ -781,6 +838,8 @@ extern "C" sdm_status sdm_transport_attach(sdm_ctx* x, void* workspace, size_t w
     T->jump = L.jump;
     T->exits = L.exits;
     T->entries = L.entries;
+    T->super_exits = L.super_exits;
+    T->super_entries = L.super_entries;
     T->start = L.start;
     T->plan_info = L.plan_info;
     x->transport = std::move(T);

@@ -142,6 +142,26 @@ def test_device_plan_equals_host_plan(sdm_mod, oracle_mod, slots):
     _assert_same(ctx, ref, "device plan")
 
 
+def test_device_plan_many_chunks(sdm_mod):
+    """A grid of 320 x 256 cells: the device plan walks 80 chunks of 1024 cells and
+    chains their exit tables in two runs; after each transport step its group count
+    equals that of the host's greedy packing of the same offsets."""
+    nx, nz, d = 320, 256, 20.0
+    pop = synth.domain_2d(seed=synth.SEEDS[6], nx=nx, ny=nz, per_cell=60)
+    x, z = synth.positions_in_cells(pop, nx, nz, d, d, seed=3)
+    ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV)
+    ctx.set_launch_config(group_slots=256)
+    ctx.attach_transport(x, z, nx, nz, d, d)
+    cx, cz = synth.eddy_courant(nx, nz, d, d, 2.0, w_max=3.0)
+    for _ in range(3):
+        ctx.transport(cx, cz, 2.0, sediment=True)
+        dev = ctx.plan()
+        ctx.set_launch_config(group_slots=512)
+        ctx.set_launch_config(group_slots=256)     # host plan from the same offsets
+        host = ctx.plan()
+        assert dev == host and dev[1] == nx * nz and dev[2] == 0
+
+
 def test_transport_errors(sdm_mod):
     nx = nz = 4
     d = 10.0
