@@ -9,8 +9,9 @@ coalescence steps (the re-sort fixes the storage slots both sides key their
 random numbers by).  Cases: attachment (re-sort by the cells of the positions),
 the single-eddy flow alone, sedimentation with particles leaving the domain,
 recycling of the leavers under the release rules, a 2D-domain run of 60 steps
-with all processes, invalid inputs, and one step of the large domain at full
-size (1024 x 1024 cells, ~134M SDs).
+with all processes, steps in which nobody or nearly everybody changes cell, the
+device launch plan against the host's (also over many chunks), invalid inputs,
+and one step of the large domain at full size (1024 x 1024 cells, ~134M SDs).
 """
 import numpy as np
 import pytest
@@ -116,6 +117,32 @@ def test_domain_2d_all_processes(sdm_mod, oracle_mod):
         ref.step_parallel(1.0, oracle_mod.GEOMETRIC, pop.seed, t)
     _assert_same(ctx, ref, "domain 2d")
     assert ref.stats[1] > 0
+
+
+def test_no_movers_and_mass_movement(sdm_mod, oracle_mod):
+    """Steps without flow or fall (nobody changes cell: the storage stays as it is),
+    then a uniform flow of Courant number 0.9 in x and z, under which nine in ten
+    particles change cell every step and those leaving the top are flagged; each
+    transport step is followed by a coalescence step, both sides bit-exact."""
+    nx, nz, d = 24, 16, 20.0
+    pop = synth.domain_2d(seed=synth.SEEDS[4], nx=nx, ny=nz, per_cell=30)
+    ctx, ref = _setup(sdm_mod, oracle_mod, pop, nx, nz, d)
+    off0, idx0 = (a.cpu().numpy().copy() for a in ctx.layout())
+    for t in range(2):
+        ctx.transport(None, None, 1.0, sediment=False)
+        ref.transport(None, None, 1.0, sediment=False)
+    off1, idx1 = (a.cpu().numpy() for a in ctx.layout())
+    assert np.array_equal(off0, off1) and np.array_equal(idx0, idx1)
+    _assert_same(ctx, ref, "no movers")
+    cx = np.full(nz * nx, 0.9)
+    cz = np.full((nz + 1) * nx, 0.9)
+    for t in range(4):
+        ctx.transport(cx, cz, 1.0, sediment=False)
+        ref.transport(cx, cz, 1.0, sediment=False)
+        ctx.step(1.0, "geometric", pop.seed, t)
+        ref.step(1.0, oracle_mod.GEOMETRIC, pop.seed, t)
+        _assert_same(ctx, ref, f"uniform flow step {t}")
+    assert (ctx.state_numpy()[0] == 0).sum() > 0      # some left through the top
 
 
 @pytest.mark.parametrize("slots", [256, 512])
