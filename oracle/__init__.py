@@ -95,6 +95,14 @@ def lib() -> ctypes.CDLL:
     L.oracle_collide_pair_fidelity.restype = None
     L.oracle_recycle_cell.argtypes = [u32, P, P]
     L.oracle_recycle_cell.restype = u32
+    L.oracle_recycle_cell_dry.argtypes = [u32, P, P, P, P]
+    L.oracle_recycle_cell_dry.restype = u32
+    L.oracle_step_dry.argtypes = [u32, P, P, P, P, dbl, i32, P, u64, u32, u32, P, u32, P, P]
+    L.oracle_step_dry.restype = i32
+    L.oracle_dry_merge.argtypes = [u64, dbl, dbl, dbl, dbl, P, P]
+    L.oracle_dry_merge.restype = None
+    L.oracle_dry_radii.argtypes = [u64, P, P]
+    L.oracle_dry_radii.restype = None
     L.oracle_sort_by_cell.argtypes = [u64, P, u32, P, P]
     L.oracle_sort_by_cell.restype = i32
     L.oracle_moments.argtypes = [u32, P, P, P, P, i32, dbl, dbl, P, P]
@@ -189,12 +197,26 @@ def collide_pair_fidelity(g: int, xi_j: int, r_j: float, xi_k: int, r_k: float):
     return int(a[0]), float(r[0]), int(a[1]), float(r[1])
 
 
-def recycle_cell(xi_cell, r_cell):
-    """Recycle one cell in place on copies; returns (xi, r, number recycled)."""
+def recycle_cell(xi_cell, r_cell, rd3_cell=None, kappa_cell=None):
+    """Recycle one cell in place on copies; returns (xi, r, number recycled), or
+    (xi, r, rd3, kappa, number recycled) with the dry attributes."""
     xi = np.array(xi_cell, dtype=np.uint64)
     r = np.array(r_cell, dtype=np.float64)
-    n = lib().oracle_recycle_cell(xi.size, _ptr(xi), _ptr(r))
-    return xi, r, int(n)
+    if rd3_cell is None:
+        n = lib().oracle_recycle_cell(xi.size, _ptr(xi), _ptr(r))
+        return xi, r, int(n)
+    rd3 = np.array(rd3_cell, dtype=np.float64)
+    kappa = np.array(kappa_cell, dtype=np.float64)
+    n = lib().oracle_recycle_cell_dry(xi.size, _ptr(xi), _ptr(r), _ptr(rd3), _ptr(kappa))
+    return xi, r, rd3, kappa, int(n)
+
+
+def dry_merge(g: int, rd3_j: float, kappa_j: float, rd3_k: float, kappa_k: float):
+    """(r_d^3, kappa) of the droplets formed by g events between j and k."""
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    lib().oracle_dry_merge(g, rd3_j, kappa_j, rd3_k, kappa_k, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def _column(v: float, d: float, n: int) -> int:
@@ -232,6 +254,19 @@ class SlotState:
         self.xi = np.ascontiguousarray(np.asarray(xi, dtype=np.uint64)[idx])
         self.r = np.ascontiguousarray(np.asarray(r, dtype=np.float64)[idx])
         self.stats = np.zeros(2, dtype=np.uint64)
+        self.rd3 = None
+        self.kappa = None
+
+    def set_dry(self, rd3, kappa):
+        """Attach the optional dry attributes (input order): r_d^3 and kappa."""
+        idx = self.id.astype(np.int64)
+        self.rd3 = np.ascontiguousarray(np.asarray(rd3, dtype=np.float64)[idx])
+        self.kappa = np.ascontiguousarray(np.asarray(kappa, dtype=np.float64)[idx])
+
+    def _dry_ptrs(self, base: int):
+        if self.rd3 is None:
+            return None, None
+        return self.rd3[base:].ctypes.data, self.kappa[base:].ctypes.data
 
     def step(self, dt: float, kind: int, seed: int, step: int, params=None,
              cells: tuple | None = None, cell_index_base: int = 0, rules: int = 0):
@@ -246,9 +281,10 @@ class SlotState:
         xi_view = self.xi[base:]
         r_view = self.r[base:]
         st = np.zeros(2, dtype=np.uint64)
-        lib().oracle_step_rules(c1 - c0, _ptr(rel), _ptr(dv), xi_view.ctypes.data,
-                                r_view.ctypes.data, dt, kind, _ptr(p), seed, step,
-                                cell_index_base + c0, _ptr(st), rules)
+        rd3_p, kappa_p = self._dry_ptrs(base)
+        lib().oracle_step_dry(c1 - c0, _ptr(rel), _ptr(dv), xi_view.ctypes.data,
+                              r_view.ctypes.data, dt, kind, _ptr(p), seed, step,
+                              cell_index_base + c0, _ptr(st), rules, rd3_p, kappa_p)
         self.stats += st
         return st
 
@@ -275,9 +311,10 @@ class SlotState:
         base = int(off[0])
         rel = np.ascontiguousarray(off - np.uint64(base))
         st = np.zeros(2, dtype=np.uint64)
-        lib().oracle_step_rules(c1 - c0, _ptr(rel), _ptr(dv), self.xi[base:].ctypes.data,
-                                self.r[base:].ctypes.data, dt, kind, _ptr(p), seed, step, c0,
-                                _ptr(st), rules)
+        rd3_p, kappa_p = self._dry_ptrs(base)
+        lib().oracle_step_dry(c1 - c0, _ptr(rel), _ptr(dv), self.xi[base:].ctypes.data,
+                              self.r[base:].ctypes.data, dt, kind, _ptr(p), seed, step, c0,
+                              _ptr(st), rules, rd3_p, kappa_p)
         return st
 
     def moments(self, k: int, r_min: float = 0.0, r_max: float = float("inf"), rho_d=None):
@@ -286,6 +323,20 @@ class SlotState:
         rho = None if rho_d is None else np.ascontiguousarray(rho_d, dtype=np.float64)
         lib().oracle_moments(self.n_cells, _ptr(self.offsets), _ptr(self.dV), _ptr(self.xi),
                              _ptr(self.r), k, r_min, r_max,
+                             None if rho is None else _ptr(rho), _ptr(out))
+        return out
+
+    def dry_moments(self, k: int, rd_min: float = 0.0, rd_max: float = float("inf"),
+                    rho_d=None):
+        """Per-cell k-th moment of the dry-radius distribution, r_d the correctly
+        rounded cube root of r_d^3; same selection and summation as ``moments``."""
+        rd = np.zeros(max(1, self.rd3.size))
+        lib().oracle_dry_radii(self.rd3.size, _ptr(self.rd3), _ptr(rd))
+        rd = np.ascontiguousarray(rd[:self.rd3.size])
+        out = np.zeros(self.n_cells)
+        rho = None if rho_d is None else np.ascontiguousarray(rho_d, dtype=np.float64)
+        lib().oracle_moments(self.n_cells, _ptr(self.offsets), _ptr(self.dV), _ptr(self.xi),
+                             _ptr(rd), k, rd_min, rd_max,
                              None if rho is None else _ptr(rho), _ptr(out))
         return out
 
@@ -328,6 +379,9 @@ class SlotState:
         self.id = np.ascontiguousarray(self.id[o])
         self.x = np.ascontiguousarray(self.x[o])
         self.z = np.ascontiguousarray(self.z[o])
+        if self.rd3 is not None:
+            self.rd3 = np.ascontiguousarray(self.rd3[o])
+            self.kappa = np.ascontiguousarray(self.kappa[o])
 
     def transport(self, cx, cz, dt: float, sediment: bool = True, params=None):
         """Advect (Courant fields cx: nz*nx, cz: (nz+1)*nx, either None), sediment,
@@ -350,6 +404,15 @@ class SlotState:
         x[self.id.astype(np.int64)] = self.x
         z[self.id.astype(np.int64)] = self.z
         return x, z
+
+    def dry_input_order(self):
+        """(r_d^3, kappa) scattered back to input order."""
+        rd3 = np.empty_like(self.rd3)
+        kappa = np.empty_like(self.kappa)
+        idx = self.id.astype(np.int64)
+        rd3[idx] = self.rd3
+        kappa[idx] = self.kappa
+        return rd3, kappa
 
     def input_order(self):
         """(xi, r) scattered back to input order."""

@@ -41,6 +41,12 @@
  *     a particle leaving [0, nz dz) gets multiplicity 0 and is clamped into
  *     the boundary row, and the storage is re-sorted by cell keeping the old
  *     storage order within a cell;
+ *   - optional dry attributes (r_d^3 and kappa, oracle_dry_merge): the
+ *     merged droplets of a collision sum r_d^3 over their constituents and
+ *     take the dry-volume-weighted mean of their kappa (the paper names the
+ *     two kinds, summed and averaged, without the weight); super-droplets
+ *     that keep their radius keep their dry attributes, recycled slots take
+ *     the donor's;
  *   - moments count live super-droplets only, the radius range is closed at
  *     both ends, and rho_d defaults to 1 (moments per unit volume) when no
  *     dry-air density is given; the summation order is fixed (see
@@ -378,6 +384,23 @@ void oracle_collide_pair_fidelity(uint64_t g, uint64_t *xi_j, double *r_j, uint6
     *xi_j = *xi_j - *xi_k;   /* zero when the multiplicities are equal */
 }
 
+/* Dry attributes of the droplets formed by g collision events between j and
+ * k (Sect. 5.1.4: extensive parameters such as r_d^3 are summed, intensive
+ * ones such as kappa averaged).  Each merged droplet holds g droplets of j and
+ * one of k: its r_d^3 is g r_d,j^3 + r_d,k^3 and its kappa the mean of the
+ * constituents' kappa weighted by their r_d^3. */
+void oracle_dry_merge(uint64_t g, double rd3_j, double kappa_j, double rd3_k, double kappa_k,
+                      double *rd3_new, double *kappa_new)
+{
+    double from_j = (double)g * rd3_j;
+    double sum = from_j + rd3_k;
+    double weighted = from_j * kappa_j;
+    double weighted_k = rd3_k * kappa_k;
+    weighted = weighted + weighted_k;
+    *rd3_new = sum;
+    *kappa_new = weighted / sum;
+}
+
 /* Recycling in one cell (the zero-multiplicity rule of Sect. 5.1.4, applied
  * within the cell).  Let z be the number of dead slots (xi = 0) and L the
  * number of live ones.  The donors are the min(z, L) live slots ranked first
@@ -402,7 +425,8 @@ static int cmp_u32(const void *pa, const void *pb)
     return a < b ? -1 : (a > b ? 1 : 0);
 }
 
-uint32_t oracle_recycle_cell(uint32_t n_slots, uint64_t *xi, double *r)
+uint32_t oracle_recycle_cell_dry(uint32_t n_slots, uint64_t *xi, double *r, double *rd3,
+                                 double *kappa)
 {
     uint32_t n = n_slots ? n_slots : 1u;
     uint32_t *dead = (uint32_t *)malloc(sizeof(uint32_t) * n);
@@ -430,6 +454,10 @@ uint32_t oracle_recycle_cell(uint32_t n_slots, uint64_t *xi, double *r)
             uint64_t half = xi[d] / 2u;
             xi[t] = half;
             r[t] = r[d];
+            if (rd3) {
+                rd3[t] = rd3[d];
+                kappa[t] = kappa[d];
+            }
             xi[d] = xi[d] - half;
         }
     }
@@ -437,6 +465,11 @@ uint32_t oracle_recycle_cell(uint32_t n_slots, uint64_t *xi, double *r)
     free(donor);
     free(live);
     return nd;
+}
+
+uint32_t oracle_recycle_cell(uint32_t n_slots, uint64_t *xi, double *r)
+{
+    return oracle_recycle_cell_dry(n_slots, xi, r, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -477,11 +510,12 @@ uint32_t oracle_cell_order(uint32_t n_slots, const uint64_t *xi, uint64_t seed,
 
 /* One step over cells [0, n_cells) stored slot-contiguously: cell c owns
  * slots [offsets[c], offsets[c+1]).  The RNG cell index of cell c is
- * cell_index_base + c.  stats[0] += pair tests, stats[1] += collisions. */
-int oracle_step_rules(uint32_t n_cells, const uint64_t *offsets, const double *dV,
-                      uint64_t *xi, double *r, double dt, int kernel, const double *params,
-                      uint64_t seed, uint32_t step, uint32_t cell_index_base, uint64_t *stats,
-                      uint32_t rules)
+ * cell_index_base + c.  stats[0] += pair tests, stats[1] += collisions.
+ * rd3 and kappa (both NULL, or both per slot) are the optional dry attributes. */
+int oracle_step_dry(uint32_t n_cells, const uint64_t *offsets, const double *dV,
+                    uint64_t *xi, double *r, double dt, int kernel, const double *params,
+                    uint64_t seed, uint32_t step, uint32_t cell_index_base, uint64_t *stats,
+                    uint32_t rules, double *rd3, double *kappa)
 {
     uint32_t max_slots = 0;
     for (uint32_t c = 0; c < n_cells; ++c) {
@@ -493,7 +527,9 @@ int oracle_step_rules(uint32_t n_cells, const uint64_t *offsets, const double *d
         uint64_t base = offsets[c];
         uint32_t n_slots = (uint32_t)(offsets[c + 1] - base);
         uint32_t cell = cell_index_base + c;
-        if (rules & ORACLE_RULE_RECYCLE) oracle_recycle_cell(n_slots, xi + base, r + base);
+        if (rules & ORACLE_RULE_RECYCLE)
+            oracle_recycle_cell_dry(n_slots, xi + base, r + base, rd3 ? rd3 + base : NULL,
+                                    kappa ? kappa + base : NULL);
         uint32_t n = oracle_cell_order(n_slots, xi + base, seed, cell, step, order);
         if (n < 2) continue;
         double scale = oracle_upscale(n);
@@ -505,20 +541,51 @@ int oracle_step_rules(uint32_t n_cells, const uint64_t *offsets, const double *d
             double K = oracle_kernel(kernel, params, r[a], r[b]);
             double p = oracle_probability(xi[j], K, dt, dV[c], scale);
             double u = oracle_pair_uniform(seed, cell, step, m);
+            uint64_t g;
+            int both_merged = 0;   /* the equal split: j takes the merged droplets too */
             if (rules & ORACLE_RULE_FIDELITY) {
-                uint64_t g = oracle_gamma_fidelity(p, u);
-                if (g > 0) stats[1] += 1;
-                oracle_collide_pair_fidelity(g, &xi[j], &r[j], &xi[k], &r[k]);
+                g = oracle_gamma_fidelity(p, u);
             } else {
-                uint64_t g = oracle_gamma(p, u, xi[j], xi[k]);
-                if (g > 0) stats[1] += 1;
-                oracle_collide_pair(g, &xi[j], &r[j], &xi[k], &r[k]);
+                g = oracle_gamma(p, u, xi[j], xi[k]);
+                both_merged = g > 0 && xi[j] <= g * xi[k];
             }
+            if (g > 0) {
+                stats[1] += 1;
+                if (rd3) {
+                    double rd3_new, kappa_new;
+                    oracle_dry_merge(g, rd3[j], kappa[j], rd3[k], kappa[k], &rd3_new, &kappa_new);
+                    rd3[k] = rd3_new;
+                    kappa[k] = kappa_new;
+                    if (both_merged) {
+                        rd3[j] = rd3_new;
+                        kappa[j] = kappa_new;
+                    }
+                }
+            }
+            if (rules & ORACLE_RULE_FIDELITY)
+                oracle_collide_pair_fidelity(g, &xi[j], &r[j], &xi[k], &r[k]);
+            else
+                oracle_collide_pair(g, &xi[j], &r[j], &xi[k], &r[k]);
         }
         stats[0] += n / 2u;
     }
     free(order);
     return 0;
+}
+
+int oracle_step_rules(uint32_t n_cells, const uint64_t *offsets, const double *dV,
+                      uint64_t *xi, double *r, double dt, int kernel, const double *params,
+                      uint64_t seed, uint32_t step, uint32_t cell_index_base, uint64_t *stats,
+                      uint32_t rules)
+{
+    return oracle_step_dry(n_cells, offsets, dV, xi, r, dt, kernel, params, seed, step,
+                           cell_index_base, stats, rules, NULL, NULL);
+}
+
+/* Dry radii from r_d^3 (correctly rounded cube roots), for the dry moments. */
+void oracle_dry_radii(uint64_t n, const double *rd3, double *rd)
+{
+    for (uint64_t i = 0; i < n; ++i) rd[i] = oracle_cbrt_rn(rd3[i]);
 }
 
 int oracle_step(uint32_t n_cells, const uint64_t *offsets, const double *dV,
