@@ -293,6 +293,42 @@ sdm_status sdm_transport_step(sdm_ctx *ctx, const double *cx, const double *cz, 
  * NULL.  Synchronises.  Errors: SDM_ESTATE (no transport attached). */
 sdm_status sdm_transport_get_positions(sdm_ctx *ctx, double *x_out, double *z_out);
 
+/* ------------------------------------------------------------------------ */
+/* Optional dry attributes (Sect. 5.1.4: on coalescence, extensive particle  */
+/* parameters such as the dry radius cubed are summed and intensive ones     */
+/* such as the hygroscopicity kappa averaged).  Each droplet formed by g     */
+/* events between j (larger multiplicity) and k holds g droplets of j and    */
+/* one of k: its r_d^3 is g r_d,j^3 + r_d,k^3 and its kappa the r_d^3-       */
+/* weighted mean of theirs, evaluated as ((g r_d,j^3) kappa_j +             */
+/* r_d,k^3 kappa_k) / (g r_d,j^3 + r_d,k^3).  The particle that takes the    */
+/* merged radius takes these values (in the equal split, both do); recycled  */
+/* slots copy the donor's; transport keeps them with their particles.        */
+/* Single-run contexts only.                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of the caller-owned device workspace sdm_dry_attach needs (32 B per
+ * super-droplet: both attributes and their re-sort targets). */
+size_t sdm_dry_workspace_bytes(uint64_t n_sd);
+
+/* Attach rd3_in (r_d^3, m^3) and kappa_in (dimensionless), dev double[n_sd]
+ * in input order; they are copied into the workspace (256-byte aligned,
+ * allocated while the context lives).  Synchronises.  Errors: SDM_EINVAL
+ * (NULL arrays while n_sd > 0, an r_d^3 not finite and > 0 or a kappa not
+ * finite and >= 0, workspace NULL or misaligned), SDM_ENOMEM (workspace too
+ * small), SDM_ESTATE (already attached). */
+sdm_status sdm_dry_attach(sdm_ctx *ctx, void *workspace, size_t ws_bytes, const double *rd3_in,
+                          const double *kappa_in);
+
+/* r_d^3 and kappa in input order (dev double[n_sd]; either output may be
+ * NULL).  Synchronises.  Errors: SDM_ESTATE (nothing attached). */
+sdm_status sdm_dry_get(sdm_ctx *ctx, double *rd3_out, double *kappa_out);
+
+/* As sdm_diag_moments for the dry radius r_d, the correctly rounded cube root
+ * of r_d^3, with the closed range [rd_min, rd_max].  Errors: as
+ * sdm_diag_moments, SDM_ESTATE (nothing attached). */
+sdm_status sdm_diag_dry_moments(sdm_ctx *ctx, uint32_t k, double rd_min, double rd_max,
+                                const double *rho_d, double *out);
+
 /* Launch plan of a context: number of wave-tier groups (runs of consecutive
  * cells processed by one wavefront), cells in them, and cells of the grid tier
  * (cells with more storage slots than a group holds, each spread over many

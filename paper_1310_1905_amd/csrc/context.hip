@@ -78,6 +78,8 @@ StepArgs base_args(const sdm_ctx* x)
     a.dV = x->dV;
     a.kp = to_kp(x->params);
     a.rules = x->rules;
+    a.rd3 = x->rd3;
+    a.kappa = x->kappa;
     a.stats = x->stats;
     a.scr_kv = x->scr_kv;
     a.scr_tmp = x->scr_tmp;
@@ -261,7 +263,7 @@ static sdm_status enqueue_recycle(sdm_ctx* x)
     if (x->n_cells == 0) return SDM_OK;
     hipLaunchKernelGGL(k_recycle, dim3(grid_for(x->n_cells, kRecycleCellsPerBlock, 1u << 16)),
                        dim3(kRecycleBlock), 0, x->stream, x->offsets, x->xi, x->r, x->n_cells,
-                       x->probe_order, x->stats + kRecycledStat);
+                       x->probe_order, x->stats + kRecycledStat, x->rd3, x->kappa);
     SDM_LAUNCHED();
     return SDM_OK;
 }
@@ -355,7 +357,7 @@ extern "C" sdm_status sdm_diag_moments(sdm_ctx* x, uint32_t k, double r_min, dou
         set_error("out must be non-NULL");
         return SDM_EINVAL;
     }
-    hipLaunchKernelGGL(k_moments, dim3(diag_grid(x->n_cells)), dim3(kDiagBlock), 0, x->stream,
+    hipLaunchKernelGGL(k_moments<false>, dim3(diag_grid(x->n_cells)), dim3(kDiagBlock), 0, x->stream,
                        x->offsets, x->dV, x->xi, x->r, x->n_cells, k, r_min, r_max, rho_d, out);
     SDM_LAUNCHED();
     return SDM_OK;

@@ -1,6 +1,6 @@
 // context.hpp -- the state of a single-run context, shared by the files that
 // implement its C ABI (context.hip: steps and queries; transport.hip: particle
-// transport between cells).
+// transport between cells; dry.hip: the optional dry attributes).
 #pragma once
 
 #include "runtime.hpp"
@@ -77,6 +77,12 @@ struct sdm_ctx {
     sdm::SortScratch sort{};
     // particle positions and the transport buffers, once attached
     std::unique_ptr<sdm::TransportState> transport;
+    // optional dry attributes (r_d^3, kappa) in storage order and their re-sort
+    // targets, once attached (caller's dry workspace)
+    double* rd3 = nullptr;
+    double* kappa = nullptr;
+    double* rd3_alt = nullptr;
+    double* kappa_alt = nullptr;
 };
 
 namespace sdm {

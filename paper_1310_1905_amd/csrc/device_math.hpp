@@ -235,6 +235,22 @@ __device__ __forceinline__ uint64_t collision_count_release(double p, double u)
     return (u < p) ? 1u : 0u;
 }
 
+// Dry attributes of the droplets formed by g events between j and k
+// (Sect. 5.1.4: extensive parameters such as r_d^3 are summed, intensive ones
+// such as kappa averaged): each merged droplet holds g droplets of j and one of
+// k, so r_d^3 = g r_d,j^3 + r_d,k^3 and kappa is the r_d^3-weighted mean.
+__device__ __forceinline__ void merge_dry(uint64_t g, double rd3_j, double kappa_j, double rd3_k,
+                                          double kappa_k, double& rd3_new, double& kappa_new)
+{
+    const double from_j = static_cast<double>(g) * rd3_j;
+    const double sum = from_j + rd3_k;
+    double weighted = from_j * kappa_j;
+    const double weighted_k = rd3_k * kappa_k;
+    weighted = weighted + weighted_k;
+    rd3_new = sum;
+    kappa_new = weighted / sum;
+}
+
 // Outcome of g > 0 events between j (xi_j >= xi_k) and k.
 struct PairState {
     uint64_t xj, xk;

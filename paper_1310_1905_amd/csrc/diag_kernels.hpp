@@ -38,7 +38,9 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// out[c] = (rho_d[c] dV[c])^-1 sum_{live i in c, r_min <= r_i <= r_max} xi_i r_i^k
+// out[c] = (rho_d[c] dV[c])^-1 sum_{live i in c, r_min <= r_i <= r_max} xi_i r_i^k;
+// with DRY, r holds r_d^3 and r_i is its correctly rounded cube root.
+template <bool DRY>
 __global__ __launch_bounds__(kDiagBlock) void k_moments(const uint32_t* __restrict__ off,
                                                         const double* __restrict__ dV,
                                                         const uint64_t* __restrict__ xi,
@@ -66,9 +68,11 @@ __global__ __launch_bounds__(kDiagBlock) void k_moments(const uint32_t* __restri
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                if (xv[t] != 0 && rv[t] >= r_min && rv[t] <= r_max) {
+                if (xv[t] == 0) continue;
+                const double rad = DRY ? cbrt_rn(rv[t]) : rv[t];
+                if (rad >= r_min && rad <= r_max) {
                     double rk = 1.0;
-                    for (uint32_t e = 0; e < k; ++e) rk = rk * rv[t];
+                    for (uint32_t e = 0; e < k; ++e) rk = rk * rad;
                     acc = acc + static_cast<double>(xv[t]) * rk;
                 }
             }

@@ -65,12 +65,15 @@ __device__ __forceinline__ uint32_t count_at_least(const uint64_t* __restrict__ 
 
 // list: uint32[n_sd] scratch, cell c uses [off[c], off[c+1]).
 // recycled: counter (nullable) incremented by the number of recycled slots.
+// rd3, kappa: optional dry attributes (nullable), copied with the radius.
 __global__ __launch_bounds__(kRecycleBlock) void k_recycle(const uint32_t* __restrict__ off,
                                                            uint64_t* __restrict__ xi,
                                                            double* __restrict__ r,
                                                            uint32_t n_cells,
                                                            uint32_t* __restrict__ list,
-                                                           unsigned long long* recycled)
+                                                           unsigned long long* recycled,
+                                                           double* __restrict__ rd3,
+                                                           double* __restrict__ kappa)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t lanes_lt = (1ull << lane) - 1ull;
@@ -145,6 +148,10 @@ __global__ __launch_bounds__(kRecycleBlock) void k_recycle(const uint32_t* __res
             const uint64_t half = x >> 1;
             xi[t] = half;
             r[t] = r[d];
+            if (rd3) {
+                rd3[t] = rd3[d];
+                kappa[t] = kappa[d];
+            }
             xi[d] = x - half;
         }
         done += nd;

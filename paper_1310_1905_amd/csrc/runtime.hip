@@ -292,7 +292,7 @@ static sdm_status launch_grid(hipStream_t s, const StepArgs& a)
 }
 
 // ------------------------------------------------------------ step launch
-template <int CAP, bool BATCHED, bool PERM>
+template <int CAP, bool BATCHED, bool PERM, bool DRY>
 static sdm_status launch_wave(hipStream_t s, const StepArgs& a, uint32_t n_groups,
                               const LaunchShape& sh)
 {
@@ -304,9 +304,9 @@ static sdm_status launch_wave(hipStream_t s, const StepArgs& a, uint32_t n_group
     }
     const dim3 grid(static_cast<uint32_t>(blocks));
     switch (sh.waves_per_block) {
-    case 1: hipLaunchKernelGGL((k_wave_groups<CAP, 1, BATCHED, PERM>), grid, dim3(64), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_wave_groups<CAP, 2, BATCHED, PERM>), grid, dim3(128), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_wave_groups<CAP, 4, BATCHED, PERM>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_wave_groups<CAP, 1, BATCHED, PERM, DRY>), grid, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_wave_groups<CAP, 2, BATCHED, PERM, DRY>), grid, dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_wave_groups<CAP, 4, BATCHED, PERM, DRY>), grid, dim3(256), 0, s, a); break;
     default: set_error("waves_per_block must be 1, 2 or 4"); return SDM_EINVAL;
     }
     SDM_LAUNCHED();
@@ -317,8 +317,15 @@ template <bool BATCHED, bool PERM>
 static sdm_status launch_wave_any(hipStream_t s, const StepArgs& a, uint32_t n_groups,
                                   const LaunchShape& sh)
 {
-    if (sh.group_slots == 256) return launch_wave<256, BATCHED, PERM>(s, a, n_groups, sh);
-    if (sh.group_slots == 512) return launch_wave<512, BATCHED, PERM>(s, a, n_groups, sh);
+    // the dry attributes exist in single runs only, and a permutation query changes nothing
+    if constexpr (!BATCHED && !PERM) {
+        if (a.rd3) {
+            if (sh.group_slots == 256) return launch_wave<256, false, false, true>(s, a, n_groups, sh);
+            if (sh.group_slots == 512) return launch_wave<512, false, false, true>(s, a, n_groups, sh);
+        }
+    }
+    if (sh.group_slots == 256) return launch_wave<256, BATCHED, PERM, false>(s, a, n_groups, sh);
+    if (sh.group_slots == 512) return launch_wave<512, BATCHED, PERM, false>(s, a, n_groups, sh);
     set_error("group_slots must be 256 or 512");
     return SDM_EINVAL;
 }

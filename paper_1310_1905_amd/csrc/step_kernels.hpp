@@ -54,6 +54,8 @@ struct InstanceRec {
 struct StepArgs {
     uint64_t* xi;                 // storage-order multiplicities
     double* r;                    // storage-order radii
+    double* rd3;                  // optional dry attributes (null, or both per slot)
+    double* kappa;
     uint64_t n_sd;                // length of xi and r
     const uint32_t* group_begin;  // wave tier: first cell of each group
     const uint32_t* group_end;    // one past the last cell
@@ -206,6 +208,22 @@ __device__ __forceinline__ void add_counts(const StepArgs& a, bool batched, uint
     }
 }
 
+// Dry attributes after g events: k (and j too in the equal split) takes the
+// merged droplets' r_d^3 and kappa.
+__device__ __forceinline__ void update_dry(const StepArgs& a, uint64_t g, uint64_t gj, uint64_t gk,
+                                           bool both)
+{
+    if (!a.rd3) return;
+    double rd3_new, kappa_new;
+    merge_dry(g, a.rd3[gj], a.kappa[gj], a.rd3[gk], a.kappa[gk], rd3_new, kappa_new);
+    a.rd3[gk] = rd3_new;
+    a.kappa[gk] = kappa_new;
+    if (both) {
+        a.rd3[gj] = rd3_new;
+        a.kappa[gj] = kappa_new;
+    }
+}
+
 // Pair test + update of one pair (a first, b second in shuffle order).
 // Writes changed super-droplets to global memory; returns whether gamma > 0.
 __device__ __forceinline__ bool collide_pair_global(const StepArgs& a, const CellJob& j,
@@ -235,6 +253,7 @@ __device__ __forceinline__ bool collide_pair_global(const StepArgs& a, const Cel
         a.xi[gk] = s.xk;
         a.r[gj] = s.rj;
     }
+    update_dry(a, g, gj, gk, s.j_changed_r);
     return true;
 }
 
@@ -321,7 +340,9 @@ __device__ __forceinline__ GroupJob resolve_group(const StepArgs& a, uint32_t c0
 
 // Apply `count` queued collisions (one per lane) starting at ring index head.
 // The pair's multiplicities and radii are re-read from global memory: nothing
-// else writes those slots during the step.
+// else writes those slots during the step.  DRY: also the dry attributes (a
+// separate instantiation, so that the kernel without them keeps its registers).
+template <bool DRY>
 __device__ __forceinline__ void flush_collisions(const StepArgs& a, const CollEntry* queue,
                                                  uint32_t head, uint32_t count, uint32_t lane)
 {
@@ -340,6 +361,7 @@ __device__ __forceinline__ void flush_collisions(const StepArgs& a, const CollEn
                 a.xi[e.gk] = s.xk;
                 a.r[e.gj] = s.rj;
             }
+            if constexpr (DRY) update_dry(a, e.g, e.gj, e.gk, s.j_changed_r);
         }
     }
 }
@@ -392,7 +414,7 @@ __device__ __forceinline__ void fetch_group(const StepArgs& a, uint64_t gi, uint
     }
 }
 
-template <int CAP, int WAVES, bool BATCHED, bool PERM>
+template <int CAP, int WAVES, bool BATCHED, bool PERM, bool DRY = false>
 __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
 {
     using Lds = GroupLds<CAP>;
@@ -664,7 +686,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
             coll += nh;
             if (q_count >= static_cast<uint32_t>(kWave)) {
                 wave_sync();
-                flush_collisions(a, L.queue, q_head, kWave, lane);
+                flush_collisions<DRY>(a, L.queue, q_head, kWave, lane);
                 q_head = (q_head + kWave) % kQueueCap;
                 q_count -= kWave;
                 wave_sync();
@@ -681,7 +703,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
     if constexpr (!PERM) {
         if (q_count > 0) {
             wave_sync();
-            flush_collisions(a, L.queue, q_head, q_count, lane);
+            flush_collisions<DRY>(a, L.queue, q_head, q_count, lane);
         }
     }
     if constexpr (!BATCHED && !PERM) {

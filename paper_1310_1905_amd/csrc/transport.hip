@@ -301,7 +301,9 @@ __global__ __launch_bounds__(kTileThreads) void k_scatter_resort(
     const uint32_t* __restrict__ count, const uint64_t* __restrict__ xi,
     const double* __restrict__ r, const uint32_t* __restrict__ id, const double* __restrict__ x,
     const double* __restrict__ z, uint64_t* __restrict__ xi_o, double* __restrict__ r_o,
-    uint32_t* __restrict__ id_o, double* __restrict__ x_o, double* __restrict__ z_o)
+    uint32_t* __restrict__ id_o, double* __restrict__ x_o, double* __restrict__ z_o,
+    const double* __restrict__ rd3, const double* __restrict__ kappa, double* __restrict__ rd3_o,
+    double* __restrict__ kappa_o)
 {
     __shared__ uint32_t s_w[kTileK * kTileWaves];
     const uint64_t ntiles = (n + kTileSlots - 1) / kTileSlots;
@@ -352,6 +354,10 @@ __global__ __launch_bounds__(kTileThreads) void k_scatter_resort(
             id_o[j] = iv[k];
             x_o[j] = xs[k];
             z_o[j] = zs[k];
+            if (rd3) {
+                rd3_o[j] = rd3[s];
+                kappa_o[j] = kappa[s];
+            }
         }
     }
 }
@@ -361,7 +367,9 @@ __global__ void k_gather_sd(uint64_t n, const uint32_t* __restrict__ order,
                             const uint32_t* __restrict__ id, const double* __restrict__ x,
                             const double* __restrict__ z, uint64_t* __restrict__ xi_o,
                             double* __restrict__ r_o, uint32_t* __restrict__ id_o,
-                            double* __restrict__ x_o, double* __restrict__ z_o)
+                            double* __restrict__ x_o, double* __restrict__ z_o,
+                            const double* __restrict__ rd3, const double* __restrict__ kappa,
+                            double* __restrict__ rd3_o, double* __restrict__ kappa_o)
 {
     for (uint64_t j = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; j < n;
          j += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
@@ -371,6 +379,10 @@ __global__ void k_gather_sd(uint64_t n, const uint32_t* __restrict__ order,
         id_o[j] = id[s];
         x_o[j] = x[s];
         z_o[j] = z[s];
+        if (rd3) {
+            rd3_o[j] = rd3[s];
+            kappa_o[j] = kappa[s];
+        }
     }
 }
 
@@ -618,6 +630,8 @@ void swap_state(sdm_ctx* x)
     std::swap(x->id, T.id_alt);
     std::swap(T.x, T.x_alt);
     std::swap(T.z, T.z_alt);
+    std::swap(x->rd3, x->rd3_alt);
+    std::swap(x->kappa, x->kappa_alt);
 }
 
 sdm_status refresh_plan(sdm_ctx* x);
@@ -632,7 +646,7 @@ sdm_status resort(sdm_ctx* x)
     if (n > 0) {
         hipLaunchKernelGGL(k_gather_sd, dim3(grid_for(n, 256, 8192)), dim3(256), 0, x->stream, n,
                            order, x->xi, x->r, x->id, T.x, T.z, T.xi_alt, T.r_alt, T.id_alt,
-                           T.x_alt, T.z_alt);
+                           T.x_alt, T.z_alt, x->rd3, x->kappa, x->rd3_alt, x->kappa_alt);
         SDM_LAUNCHED();
         swap_state(x);
     }
@@ -671,7 +685,8 @@ sdm_status resort_moved(sdm_ctx* x)
     SDM_LAUNCHED();
     hipLaunchKernelGGL(k_scatter_resort, tile_grid, tile_block, 0, st, n, T.cell, T.tcnt,
                        x->offsets, T.off_alt, T.in_low, T.mlo, inv, T.inc_off, T.count, x->xi,
-                       x->r, x->id, T.x, T.z, T.xi_alt, T.r_alt, T.id_alt, T.x_alt, T.z_alt);
+                       x->r, x->id, T.x, T.z, T.xi_alt, T.r_alt, T.id_alt, T.x_alt, T.z_alt,
+                       x->rd3, x->kappa, x->rd3_alt, x->kappa_alt);
     SDM_LAUNCHED();
     swap_state(x);
     std::swap(x->offsets, T.off_alt);

@@ -84,6 +84,10 @@ def lib() -> ctypes.CDLL:
         "sdm_transport_attach": (ctypes.c_int, [_P, _P, _sz, _u32, _u32, _dbl, _dbl, _P, _P]),
         "sdm_transport_step": (ctypes.c_int, [_P, _P, _P, _dbl, ctypes.c_int]),
         "sdm_transport_get_positions": (ctypes.c_int, [_P, _P, _P]),
+        "sdm_dry_workspace_bytes": (_sz, [_u64]),
+        "sdm_dry_attach": (ctypes.c_int, [_P, _P, _sz, _P, _P]),
+        "sdm_dry_get": (ctypes.c_int, [_P, _P, _P]),
+        "sdm_diag_dry_moments": (ctypes.c_int, [_P, _u32, _dbl, _dbl, _P, _P]),
         "sdm_diag_sd_conc": (ctypes.c_int, [_P, _P]),
         "sdm_diag_moments": (ctypes.c_int, [_P, _u32, _dbl, _dbl, _P, _P]),
         "sdm_probe_probability": (ctypes.c_int, [_P, _dbl, ctypes.c_int, _u64, _u64, _P, _P]),
@@ -224,6 +228,40 @@ class Context:
         _check(lib().sdm_transport_get_positions(self._ctx, _dptr(x), _dptr(z)),
                "sdm_transport_get_positions")
         return x[: self.n_sd], z[: self.n_sd]
+
+    def attach_dry(self, rd3, kappa):
+        """Optional dry attributes (input order): r_d^3 (m^3) and kappa."""
+        L = lib()
+        rd3_t = torch.as_tensor(rd3, dtype=torch.float64).to(self.device).contiguous()
+        kappa_t = torch.as_tensor(kappa, dtype=torch.float64).to(self.device).contiguous()
+        ws_bytes = int(L.sdm_dry_workspace_bytes(self.n_sd))
+        self.dry_workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.dry_workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        torch.cuda.synchronize(self.device)
+        _check(L.sdm_dry_attach(self._ctx, aligned, ws_bytes + 256 - (aligned - base),
+                                _dptr(rd3_t), _dptr(kappa_t)), "sdm_dry_attach")
+
+    def dry(self):
+        """(r_d^3, kappa) float64 tensors in input order."""
+        rd3 = torch.empty(max(1, self.n_sd), dtype=torch.float64, device=self.device)
+        kappa = torch.empty(max(1, self.n_sd), dtype=torch.float64, device=self.device)
+        torch.cuda.synchronize(self.device)
+        _check(lib().sdm_dry_get(self._ctx, _dptr(rd3), _dptr(kappa)), "sdm_dry_get")
+        return rd3[: self.n_sd], kappa[: self.n_sd]
+
+    def dry_moments(self, k: int, rd_min: float = 0.0, rd_max: float = float("inf"),
+                    rho_d=None):
+        """Per-cell k-th dry-radius moment over r_d in [rd_min, rd_max]."""
+        out = torch.empty(max(1, self.n_cells), dtype=torch.float64, device=self.device)
+        rho = None
+        if rho_d is not None:
+            rho = torch.as_tensor(rho_d, dtype=torch.float64).to(self.device).contiguous()
+        torch.cuda.synchronize(self.device)
+        _check(lib().sdm_diag_dry_moments(self._ctx, int(k), float(rd_min), float(rd_max),
+                                          _dptr(rho), _dptr(out)), "sdm_diag_dry_moments")
+        torch.cuda.synchronize(self.device)
+        return out[: self.n_cells]
 
     def set_rules(self, rules: int):
         """SDM rule flags (RULE_RELEASE | RULE_RECYCLE) for every later step."""
