@@ -37,6 +37,7 @@ BYTES_PER_SD = 16
 BYTES_PER_CELL = 12
 BYTES_PER_COLLISION = 16
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_wave_groups_large_domain.txt")
+SQ_FILE = os.path.join(ROOT, "profiles", "sq_k_wave_groups_large_domain.txt")
 KERNEL_SOURCES = ["paper_1310_1905_amd/csrc/step_kernels.hpp",
                   "paper_1310_1905_amd/csrc/device_math.hpp"]
 
@@ -49,13 +50,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _profile_value(path: str, key: str):
+    """A value from a committed rocprofv3 summary, if the summary was taken on the
+    current kernel source."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -63,9 +64,21 @@ def measured_traffic():
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
+        return float(vals[key].split()[0])
+    except (KeyError, ValueError, IndexError):
         return None
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE,
+    calibrated with a copy kernel)."""
+    return _profile_value(TRAFFIC_FILE, "hbm_bytes_per_launch")
+
+
+def measured_valu_busy():
+    """Fraction of the SIMDs' issue cycles the dominant kernel fills with VALU
+    instructions (rocprofv3 SQ_INSTS_VALU, 4 cycles per wave64 instruction)."""
+    return _profile_value(SQ_FILE, "valu_issue_busy_frac")
 
 
 def log(msg):
@@ -145,7 +158,8 @@ def bench_large(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_wave_groups", "algorithmic_bytes_per_launch": alg_bytes,
-                     "mean_launch_ms": launch_ms},
+                     "mean_launch_ms": launch_ms,
+                     "valu_issue_busy_frac": measured_valu_busy()},
     }
     ctx.close()
     del ctx
