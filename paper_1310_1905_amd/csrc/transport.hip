@@ -126,14 +126,64 @@ __device__ __forceinline__ uint64_t tile_slot(uint64_t t, uint32_t k)
     return t * kTileSlots + k * kTileThreads + threadIdx.x;
 }
 
-// One transport step of every super-droplet (storage order).  cellm[s] gets the
-// new cell, with kMovedBit set if it differs from the old one; tcnt[t] the
-// number of such movers in tile t.
+// The flow of one transport step.
+struct Flow {
+    uint32_t nx, nz;
+    double dx, dz, dt, Lx, Lz;
+    const double* cx;   // Courant numbers on the x edges (nz * nx), or null
+    const double* cz;   // on the z edges ((nz + 1) * nx), or null
+    int sediment;
+    KernelParams kp;
+};
+
+// New position of the particle at (x0, z0) with radius r: advection from the
+// Courant numbers of its time-level-n cell, then the fall, the periodic wrap in
+// x, and a clamp into the boundary row for a particle that left through the
+// bottom or the top (*left).  *cell_old is that time-level-n cell.
+__device__ __forceinline__ void move_particle(const Flow& f, double x0, double z0, double r,
+                                              double& xn, double& zn, bool& left,
+                                              uint32_t& cell_old)
+{
+    const uint32_t i = column_of(x0, f.dx, f.nx);
+    const uint32_t k = column_of(z0, f.dz, f.nz);
+    xn = x0;
+    zn = z0;
+    if (f.cx) {
+        const double l = f.cx[static_cast<uint64_t>(k) * f.nx + i];
+        const double rr = f.cx[static_cast<uint64_t>(k) * f.nx + (i + 1u == f.nx ? 0u : i + 1u)];
+        xn = advect_1d(x0, f.dx, i, l, rr);
+    }
+    if (f.cz) {
+        const double b = f.cz[static_cast<uint64_t>(k) * f.nx + i];
+        const double tp = f.cz[static_cast<uint64_t>(k + 1u) * f.nx + i];
+        zn = advect_1d(z0, f.dz, k, b, tp);
+    }
+    if (f.sediment) zn = zn - terminal_velocity(f.kp, r) * f.dt;
+    if (xn < 0.0) {
+        xn = xn + f.Lx;
+        if (xn >= f.Lx) xn = 0.0;
+    } else if (xn >= f.Lx) {
+        xn = xn - f.Lx;
+    }
+    left = false;
+    if (zn < 0.0) {
+        left = true;
+        zn = 0.0;
+    } else if (zn >= f.Lz) {
+        left = true;
+        zn = static_cast<double>(f.nz - 1u) * f.dz;
+    }
+    cell_old = i + f.nx * k;
+}
+
+// One transport step of every super-droplet (storage order): leavers get xi = 0,
+// cellm[s] the new cell, with kMovedBit set if it differs from the old one, and
+// tcnt[t] the number of such movers in tile t.  The new positions are not stored
+// here: the re-sort scatter computes them again as it writes every particle out.
 __global__ __launch_bounds__(kTileThreads) void k_transport(
-    uint64_t n, uint32_t nx, uint32_t nz, double dx, double dz, const double* __restrict__ cx,
-    const double* __restrict__ cz, double dt, int sediment, KernelParams kp, double Lx, double Lz,
-    double* __restrict__ x, double* __restrict__ z, uint64_t* __restrict__ xi,
-    const double* __restrict__ r, uint32_t* __restrict__ cellm, uint32_t* __restrict__ tcnt)
+    uint64_t n, Flow f, const double* __restrict__ x, const double* __restrict__ z,
+    uint64_t* __restrict__ xi, const double* __restrict__ r, uint32_t* __restrict__ cellm,
+    uint32_t* __restrict__ tcnt)
 {
     __shared__ uint32_t s_w[kTileK * kTileWaves];
     const uint64_t ntiles = (n + kTileSlots - 1) / kTileSlots;
@@ -148,7 +198,7 @@ __global__ __launch_bounds__(kTileThreads) void k_transport(
             if (s < n) {
                 x0[k] = x[s];
                 z0[k] = z[s];
-                if (sediment) rv[k] = r[s];
+                if (f.sediment) rv[k] = r[s];
             }
         }
         bool moved[kTileK];
@@ -157,42 +207,33 @@ __global__ __launch_bounds__(kTileThreads) void k_transport(
             const uint64_t s = tile_slot(t, k);
             moved[k] = false;
             if (s >= n) continue;
-            const uint32_t i = column_of(x0[k], dx, nx);
-            const uint32_t kk = column_of(z0[k], dz, nz);
-            double xn = x0[k], zn = z0[k];
-            if (cx) {
-                const double l = cx[static_cast<uint64_t>(kk) * nx + i];
-                const double rr = cx[static_cast<uint64_t>(kk) * nx + (i + 1u == nx ? 0u : i + 1u)];
-                xn = advect_1d(x0[k], dx, i, l, rr);
-            }
-            if (cz) {
-                const double b = cz[static_cast<uint64_t>(kk) * nx + i];
-                const double tp = cz[static_cast<uint64_t>(kk + 1u) * nx + i];
-                zn = advect_1d(z0[k], dz, kk, b, tp);
-            }
-            if (sediment) zn = zn - terminal_velocity(kp, rv[k]) * dt;
-            if (xn < 0.0) {
-                xn = xn + Lx;
-                if (xn >= Lx) xn = 0.0;
-            } else if (xn >= Lx) {
-                xn = xn - Lx;
-            }
-            if (zn < 0.0) {
-                xi[s] = 0;
-                zn = 0.0;
-            } else if (zn >= Lz) {
-                xi[s] = 0;
-                zn = static_cast<double>(nz - 1u) * dz;
-            }
-            x[s] = xn;
-            z[s] = zn;
-            const uint32_t c_new = column_of(xn, dx, nx) + nx * column_of(zn, dz, nz);
-            moved[k] = c_new != i + nx * kk;
+            double xn, zn;
+            bool left;
+            uint32_t c_old;
+            move_particle(f, x0[k], z0[k], rv[k], xn, zn, left, c_old);
+            if (left) xi[s] = 0;
+            const uint32_t c_new = column_of(xn, f.dx, f.nx) + f.nx * column_of(zn, f.dz, f.nz);
+            moved[k] = c_new != c_old;
             cellm[s] = c_new | (moved[k] ? kMovedBit : 0u);
         }
         uint32_t pre[kTileK], tot = 0;
         tile_prefix(moved, pre, s_w, &tot);
         if (threadIdx.x == 0) tcnt[t] = tot;
+    }
+}
+
+// The new positions in place (a step in which no particle changed cell).
+__global__ void k_apply_positions(uint64_t n, Flow f, double* __restrict__ x,
+                                  double* __restrict__ z, const double* __restrict__ r)
+{
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        double xn, zn;
+        bool left;
+        uint32_t c_old;
+        move_particle(f, x[s], z[s], f.sediment ? r[s] : 0.0, xn, zn, left, c_old);
+        x[s] = xn;
+        z[s] = zn;
     }
 }
 
@@ -288,13 +329,13 @@ __global__ void k_invert_order(uint32_t m_tot, const uint32_t* __restrict__ orde
         inv[order[q]] = static_cast<uint32_t>(q);
 }
 
-// Every particle to its new slot, reading the old storage in order.  A stayer
-// goes after the cell's incoming movers from lower cells, at its rank among the
-// cell's stayers; a mover (compacted index e, sorted position inv[e]) to its
-// rank among the new cell's incoming movers, after the stayers if it comes from
-// a higher cell.
+// Every particle to its new slot, reading the old storage in order, with its
+// new position.  A stayer goes after the cell's incoming movers from lower
+// cells, at its rank among the cell's stayers; a mover (compacted index e,
+// sorted position inv[e]) to its rank among the new cell's incoming movers,
+// after the stayers if it comes from a higher cell.
 __global__ __launch_bounds__(kTileThreads) void k_scatter_resort(
-    uint64_t n, const uint32_t* __restrict__ cellm, const uint32_t* __restrict__ tpre,
+    uint64_t n, Flow f, const uint32_t* __restrict__ cellm, const uint32_t* __restrict__ tpre,
     const uint32_t* __restrict__ old_off, const uint32_t* __restrict__ new_off,
     const uint32_t* __restrict__ in_low, const uint32_t* __restrict__ mlo,
     const uint32_t* __restrict__ inv, const uint32_t* __restrict__ inc_off,
@@ -349,11 +390,15 @@ __global__ __launch_bounds__(kTileThreads) void k_scatter_resort(
                 const uint32_t stayers = count[c] - (inc_off[c + 1] - ib);
                 j = static_cast<uint64_t>(new_off[c]) + rank + (rank >= in_low[c] ? stayers : 0u);
             }
+            double xn, zn;
+            bool left;
+            uint32_t c_old;
+            move_particle(f, xs[k], zs[k], rv[k], xn, zn, left, c_old);
             xi_o[j] = xv[k];
             r_o[j] = rv[k];
             id_o[j] = iv[k];
-            x_o[j] = xs[k];
-            z_o[j] = zs[k];
+            x_o[j] = xn;
+            z_o[j] = zn;
             if (rd3) {
                 rd3_o[j] = rd3[s];
                 kappa_o[j] = kappa[s];
@@ -653,8 +698,9 @@ sdm_status resort(sdm_ctx* x)
     return refresh_plan(x);
 }
 
-// The same order after a transport step, sorting only the movers.
-sdm_status resort_moved(sdm_ctx* x)
+// The same order after a transport step, sorting only the movers; the
+// particles are written out with their new positions.
+sdm_status resort_moved(sdm_ctx* x, const Flow& f)
 {
     TransportState& T = *x->transport;
     const uint64_t n = x->n_sd;
@@ -668,7 +714,13 @@ sdm_status resort_moved(sdm_ctx* x)
     uint32_t m_tot = 0;
     SDM_HIP(hipMemcpyAsync(&m_tot, T.tcnt + ntiles, sizeof(m_tot), hipMemcpyDeviceToHost, st));
     SDM_HIP(hipStreamSynchronize(st));
-    if (m_tot == 0) return SDM_OK;   // nobody changed cell: storage, offsets and plan stay
+    if (m_tot == 0) {
+        // nobody changed cell: storage, offsets and plan stay; positions move in place
+        hipLaunchKernelGGL(k_apply_positions, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, f,
+                           T.x, T.z, x->r);
+        SDM_LAUNCHED();
+        return SDM_OK;
+    }
     hipLaunchKernelGGL(k_compact_movers, tile_grid, tile_block, 0, st, n, T.cell, T.tcnt,
                        T.mk, T.mv);
     SDM_LAUNCHED();
@@ -683,7 +735,7 @@ sdm_status resort_moved(sdm_ctx* x)
     hipLaunchKernelGGL(k_invert_order, dim3(grid_for(m_tot, 256, 8192)), dim3(256), 0, st, m_tot,
                        order, inv);
     SDM_LAUNCHED();
-    hipLaunchKernelGGL(k_scatter_resort, tile_grid, tile_block, 0, st, n, T.cell, T.tcnt,
+    hipLaunchKernelGGL(k_scatter_resort, tile_grid, tile_block, 0, st, n, f, T.cell, T.tcnt,
                        x->offsets, T.off_alt, T.in_low, T.mlo, inv, T.inc_off, T.count, x->xi,
                        x->r, x->id, T.x, T.z, T.xi_alt, T.r_alt, T.id_alt, T.x_alt, T.z_alt,
                        x->rd3, x->kappa, x->rd3_alt, x->kappa_alt);
@@ -888,15 +940,26 @@ extern "C" sdm_status sdm_transport_step(sdm_ctx* x, const double* cx, const dou
         }
     }
     const uint64_t n = x->n_sd;
+    Flow f;
+    f.nx = T.nx;
+    f.nz = T.nz;
+    f.dx = T.dx;
+    f.dz = T.dz;
+    f.dt = dt;
+    f.Lx = static_cast<double>(T.nx) * T.dx;
+    f.Lz = static_cast<double>(T.nz) * T.dz;
+    f.cx = cx;
+    f.cz = cz;
+    f.sediment = sediment ? 1 : 0;
+    f.kp = to_kp(x->params);
     if (n > 0) {
         const uint64_t ntiles = (n + kTileSlots - 1) / kTileSlots;
         hipLaunchKernelGGL(k_transport, dim3(static_cast<uint32_t>(ntiles < 8192u ? ntiles : 8192u)),
-                           dim3(kTileThreads), 0, x->stream, n, T.nx, T.nz, T.dx, T.dz, cx, cz, dt,
-                           sediment ? 1 : 0, to_kp(x->params), static_cast<double>(T.nx) * T.dx,
-                           static_cast<double>(T.nz) * T.dz, T.x, T.z, x->xi, x->r, T.cell, T.tcnt);
+                           dim3(kTileThreads), 0, x->stream, n, f, T.x, T.z, x->xi, x->r, T.cell,
+                           T.tcnt);
         SDM_LAUNCHED();
     }
-    return resort_moved(x);
+    return resort_moved(x, f);
 }
 
 extern "C" sdm_status sdm_transport_get_positions(sdm_ctx* x, double* x_out, double* z_out)
