@@ -119,6 +119,37 @@ def test_grid_tier_cells(sdm_mod, oracle_mod, kernel):
         assert np.array_equal(order[off[c]:off[c] + exp.size], exp), c
 
 
+def test_grid_tier_plan_transitions(sdm_mod, oracle_mod):
+    """Grid cells at the sizes where the digit bits or the slot-chunk size of the
+    grid tier change (257, 1024/1025, 2048/2049, 4097, 65537 and 2^20 + 1 slots,
+    the last with 4096-slot chunks), with dead slots: pairing order and two steps
+    bit-exact."""
+    g = np.random.default_rng(77)
+    sizes = [257, 1024, 1025, 2048, 2049, 4097, 65537, (1 << 20) + 1, 100]
+    cell = np.repeat(np.arange(len(sizes), dtype=np.uint32), sizes)
+    n = cell.size
+    xi = g.integers(1, 40, n).astype(np.uint64)
+    xi[g.random(n) < 0.05] = 0
+    r = np.exp(g.uniform(np.log(5e-6), np.log(2e-3), n))
+    dV = np.array([1e-2, 1e-1, 1e-1, 1.0, 1.0, 1.0, 10.0, 1e3, 1e-3])
+    ctx = sdm_mod.Context(cell, xi, r, dV)
+    ctx.set_launch_config(group_slots=256)
+    assert ctx.plan()[1:] == (1, len(sizes) - 1)
+    ref = oracle_mod.SlotState(cell, xi, r, dV)
+    order, nlive = ctx.permutation(seed=5, step=2)
+    order, nlive = order.cpu().numpy(), nlive.cpu().numpy()
+    off = ref.offsets.astype(np.int64)
+    for c in range(len(sizes)):
+        exp = oracle_mod.cell_order(ref.xi[off[c]:off[c + 1]], 5, c, 2)
+        assert nlive[c] == exp.size
+        assert np.array_equal(order[off[c]:off[c] + exp.size], exp), sizes[c]
+    for t in range(2):
+        ctx.step(2.0, "geometric", 9, t)
+        ref.step_parallel(2.0, oracle_mod.GEOMETRIC, 9, t, threads=9)
+    _assert_same(ctx, ref, "grid plan transitions")
+    assert ref.stats[1] > 0
+
+
 def test_grid_tier_huge_cell(sdm_mod, oracle_mod):
     """One cell of 2^23 + 1000 storage slots next to a 700-slot one: its 4096
     digit buckets hold about 2048 live entries each, so buckets within and beyond
