@@ -25,7 +25,7 @@ struct CtxLayout {
     unsigned int* err;
     // probe: pairing order, live counts and the running maximum of P_ij
     uint32_t* probe_order;
-    uint32_t* probe_nlive;
+    double* probe_cell;
     unsigned long long* probe_max;
     // scratch (grid-tier sort arrays during steps; sort-by-cell arrays during init)
     uint64_t* scr_kv;
@@ -51,7 +51,7 @@ CtxLayout layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t c)
     L.stats = cv.take<unsigned long long>(uint64_t(kStatSlots) * kStatStride);
     L.err = cv.take<unsigned int>(64);
     L.probe_order = cv.take<uint32_t>(n);
-    L.probe_nlive = cv.take<uint32_t>(c);
+    L.probe_cell = cv.take<double>(c);
     L.probe_max = cv.take<unsigned long long>(32);
     // the scratch region is shared by the step scratch and the init sort
     const uintptr_t scratch_begin = cv.cur;
@@ -217,7 +217,7 @@ extern "C" sdm_status sdm_init(sdm_ctx** out, void* stream, void* workspace, siz
     x->stats = L.stats;
     x->err = L.err;
     x->probe_order = L.probe_order;
-    x->probe_nlive = L.probe_nlive;
+    x->probe_cell = L.probe_cell;
     x->probe_max = L.probe_max;
     x->scr_kv = L.scr_kv;
     x->scr_tmp = L.scr_tmp;
@@ -320,12 +320,6 @@ static uint32_t diag_grid(uint32_t n_cells)
     return grid_for(n_cells, kDiagCellsPerBlock, 1u << 20);
 }
 
-// The probe ends in one global atomic per workgroup: fewer, longer-lived workgroups.
-static uint32_t probe_grid(uint32_t n_cells)
-{
-    return grid_for(n_cells, kDiagCellsPerBlock, 1u << 14);
-}
-
 extern "C" sdm_status sdm_diag_sd_conc(sdm_ctx* x, uint32_t* out)
 {
     SDM_TRY(check_ctx(x));
@@ -363,7 +357,9 @@ extern "C" sdm_status sdm_diag_moments(sdm_ctx* x, uint32_t k, double r_min, dou
     return SDM_OK;
 }
 
-// Enqueue the probe of step `step`; the maximum lands in x->probe_max.
+// Enqueue the probe of step `step`: the probe mode of the step kernels writes the
+// largest P_ij of every cell (into cell_max, or the context's scratch), then one
+// reduction puts the overall maximum into x->probe_max.
 static sdm_status enqueue_probe(sdm_ctx* x, double dt, sdm_kernel kernel, uint64_t seed,
                                 uint64_t step, double* cell_max)
 {
@@ -373,15 +369,18 @@ static sdm_status enqueue_probe(sdm_ctx* x, double dt, sdm_kernel kernel, uint64
                        0ull);
     SDM_LAUNCHED();
     if (x->n_cells == 0) return SDM_OK;
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(x->n_cells, 256, 4096)), dim3(256), 0,
-                       x->stream, x->probe_nlive, uint64_t(x->n_cells), 0u);
+    double* cm = cell_max ? cell_max : x->probe_cell;
+    // grid-tier cells take atomic maxima: every entry starts at +0.0
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(x->n_cells, 256, 4096)), dim3(256), 0,
+                       x->stream, reinterpret_cast<unsigned long long*>(cm),
+                       uint64_t(x->n_cells), 0ull);
     SDM_LAUNCHED();
-    a.perm_out = x->probe_order;
-    a.nlive_out = x->probe_nlive;
-    SDM_TRY(launch(x, a, true));
-    hipLaunchKernelGGL(k_probe_pairs, dim3(probe_grid(x->n_cells)), dim3(kDiagBlock), 0, x->stream,
-                       x->offsets, x->dV, x->xi, x->r, x->probe_order, x->probe_nlive, x->n_cells,
-                       static_cast<uint32_t>(kernel), a.kp, dt, cell_max, x->probe_max);
+    a.cell_max = cm;
+    a.stats = nullptr;
+    SDM_TRY(launch_step(x->stream, a, x->group_begin, x->group_end, x->n_groups, x->shape, false,
+                        false, true));
+    hipLaunchKernelGGL(k_max_reduce, dim3(grid_for(x->n_cells, kDiagBlock, 1024)),
+                       dim3(kDiagBlock), 0, x->stream, cm, x->n_cells, x->probe_max);
     SDM_LAUNCHED();
     return SDM_OK;
 }

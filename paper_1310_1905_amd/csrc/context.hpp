@@ -61,7 +61,7 @@ struct sdm_ctx {
     unsigned long long* stats = nullptr;
     unsigned int* err = nullptr;
     uint32_t* probe_order = nullptr;
-    uint32_t* probe_nlive = nullptr;
+    double* probe_cell = nullptr;       // probe: largest P_ij per cell (when the caller keeps none)
     unsigned long long* probe_max = nullptr;
     uint64_t* scr_kv = nullptr;
     uint64_t* scr_tmp = nullptr;

@@ -1,7 +1,8 @@
 // diag_kernels.hpp -- gridded diagnostics of the particle-based scheme
-// (Sect. 5.2: super-droplet concentration and radius moments per cell) and the
-// collision-probability probe (largest P_ij of eq. (P_ij) over the pairs of a
-// step), as segmented reductions over the cell-sorted storage.
+// (Sect. 5.2: super-droplet concentration and radius moments per cell), as
+// segmented reductions over the cell-sorted storage, and the final maximum of
+// the collision-probability probe (whose per-cell maxima the probe mode of the
+// step kernels writes).
 //
 // One wavefront per cell.  Lane l accumulates the cell's local slots
 // l, l+64, l+128, ... in ascending order; the 64 partial sums are then folded
@@ -107,41 +108,19 @@ __global__ __launch_bounds__(kDiagBlock) void k_sd_conc(const uint32_t* __restri
     }
 }
 
-// Largest P_ij per cell over the pairs (order[2m], order[2m+1]), m < n_live/2,
-// of a pairing written by the permutation launch; the maximum over all cells
-// goes to *gmax as the bit pattern of a non-negative double.
-__global__ __launch_bounds__(kDiagBlock) void k_probe_pairs(
-    const uint32_t* __restrict__ off, const double* __restrict__ dV,
-    const uint64_t* __restrict__ xi, const double* __restrict__ r,
-    const uint32_t* __restrict__ order, const uint32_t* __restrict__ nlive, uint32_t n_cells,
-    uint32_t kernel, KernelParams kp, double dt, double* __restrict__ cell_max,
-    unsigned long long* __restrict__ gmax)
+// *gmax = max(*gmax, max of v[0, n)) for non-negative doubles, as the bit
+// pattern (which orders like the value); one atomic per workgroup.
+__global__ __launch_bounds__(kDiagBlock) void k_max_reduce(const double* __restrict__ v, uint32_t n,
+                                                          unsigned long long* __restrict__ gmax)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kDiagCellsPerBlock;
-    double wave_best = 0.0;
-    for (uint64_t c = static_cast<uint64_t>(blockIdx.x) * kDiagCellsPerBlock + threadIdx.x / 64u;
-         c < n_cells; c += stride) {
-        const uint32_t b = off[c], n = nlive[c];
-        double best = 0.0;
-        if (n >= 2) {
-            const double scale = upscale_factor(n);
-            const double dVc = dV[c];
-            for (uint32_t m = lane; m < n / 2u; m += 64u) {
-                const uint32_t ia = b + order[b + 2u * m], ib = b + order[b + 2u * m + 1u];
-                const uint64_t xa = xi[ia], xb = xi[ib];
-                const double K = collection_kernel(kernel, kp, r[ia], r[ib]);
-                const double p = collision_probability(xa >= xb ? xa : xb, K, dt, dVc, scale);
-                best = fmax(best, p);
-            }
-        }
-        best = wave_max(best);
-        if (lane == 0 && cell_max) cell_max[c] = best;
-        wave_best = fmax(wave_best, best);
-    }
-    // one atomic per workgroup (a single counter word takes every update in turn)
+    double best = 0.0;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kDiagBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kDiagBlock)
+        best = fmax(best, v[i]);
+    best = wave_max(best);
     __shared__ double s_best[kDiagCellsPerBlock];
-    if (lane == 0) s_best[threadIdx.x / 64u] = wave_best;
+    if (lane == 0) s_best[threadIdx.x / 64u] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
         double b = s_best[0];

@@ -262,7 +262,7 @@ void grid_args(const GridArrays& g, StepArgs* a)
     a->gtilesum = g.gtilesum;
 }
 
-template <bool BATCHED, bool PERM>
+template <bool BATCHED, bool PERM, bool PROBE>
 static sdm_status launch_grid(hipStream_t s, const StepArgs& a)
 {
     const dim3 blk(kGridBlock);
@@ -270,9 +270,9 @@ static sdm_status launch_grid(hipStream_t s, const StepArgs& a)
     SDM_LAUNCHED();
     hipLaunchKernelGGL(k_grid_tile_sums, dim3(a.n_gtile), blk, 0, s, a);
     SDM_LAUNCHED();
-    if (PERM) {
+    if (PERM || PROBE) {
         StepArgs b = a;
-        b.stats = nullptr;   // no counters from a permutation query
+        b.stats = nullptr;   // no counters from a permutation query or a probe
         hipLaunchKernelGGL((k_grid_tile_offsets<false>), dim3((a.n_grid + kGridBlock - 1) / kGridBlock),
                            blk, 0, s, b);
     } else {
@@ -286,13 +286,13 @@ static sdm_status launch_grid(hipStream_t s, const StepArgs& a)
     SDM_LAUNCHED();
     hipLaunchKernelGGL(k_grid_bucket_sort, dim3(a.n_gbucket), blk, 0, s, a);
     SDM_LAUNCHED();
-    hipLaunchKernelGGL((k_grid_pairs<BATCHED, PERM>), dim3(a.n_gpchunk), blk, 0, s, a);
+    hipLaunchKernelGGL((k_grid_pairs<BATCHED, PERM, PROBE>), dim3(a.n_gpchunk), blk, 0, s, a);
     SDM_LAUNCHED();
     return SDM_OK;
 }
 
 // ------------------------------------------------------------ step launch
-template <int CAP, bool BATCHED, bool PERM, bool DRY>
+template <int CAP, bool BATCHED, bool PERM, bool DRY, bool PROBE = false>
 static sdm_status launch_wave(hipStream_t s, const StepArgs& a, uint32_t n_groups,
                               const LaunchShape& sh)
 {
@@ -304,9 +304,9 @@ static sdm_status launch_wave(hipStream_t s, const StepArgs& a, uint32_t n_group
     }
     const dim3 grid(static_cast<uint32_t>(blocks));
     switch (sh.waves_per_block) {
-    case 1: hipLaunchKernelGGL((k_wave_groups<CAP, 1, BATCHED, PERM, DRY>), grid, dim3(64), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_wave_groups<CAP, 2, BATCHED, PERM, DRY>), grid, dim3(128), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_wave_groups<CAP, 4, BATCHED, PERM, DRY>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_wave_groups<CAP, 1, BATCHED, PERM, DRY, PROBE>), grid, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_wave_groups<CAP, 2, BATCHED, PERM, DRY, PROBE>), grid, dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_wave_groups<CAP, 4, BATCHED, PERM, DRY, PROBE>), grid, dim3(256), 0, s, a); break;
     default: set_error("waves_per_block must be 1, 2 or 4"); return SDM_EINVAL;
     }
     SDM_LAUNCHED();
@@ -330,10 +330,37 @@ static sdm_status launch_wave_any(hipStream_t s, const StepArgs& a, uint32_t n_g
     return SDM_EINVAL;
 }
 
+// The probe of a single run (largest P_ij per cell into base.cell_max).
+static sdm_status launch_wave_probe(hipStream_t s, const StepArgs& a, uint32_t n_groups,
+                                    const LaunchShape& sh)
+{
+    if (sh.group_slots == 256) return launch_wave<256, false, false, false, true>(s, a, n_groups, sh);
+    if (sh.group_slots == 512) return launch_wave<512, false, false, false, true>(s, a, n_groups, sh);
+    set_error("group_slots must be 256 or 512");
+    return SDM_EINVAL;
+}
+
 sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* group_begin,
                        const uint32_t* group_end, uint32_t n_groups, const LaunchShape& shape,
-                       bool batched, bool perm)
+                       bool batched, bool perm, bool probe)
 {
+    if (probe) {
+        if (batched || perm) {
+            set_error("a probe is a single-run launch");
+            return SDM_EINVAL;
+        }
+        if (n_groups > 0) {
+            StepArgs a = base;
+            a.group_begin = group_begin;
+            a.group_end = group_end;
+            a.n_groups = n_groups;
+            a.groups_per_wave = shape.groups_per_wave;
+            a.xcd_remap = shape.xcd_remap;
+            SDM_TRY(launch_wave_probe(s, a, n_groups, shape));
+        }
+        if (base.n_grid > 0) SDM_TRY((launch_grid<false, false, true>(s, base)));
+        return SDM_OK;
+    }
     if (n_groups > 0) {
         StepArgs a = base;
         a.group_begin = group_begin;
@@ -347,8 +374,10 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
                           : launch_wave_any<false, false>(s, a, n_groups, shape));
     }
     if (base.n_grid > 0) {
-        if (batched) SDM_TRY(perm ? launch_grid<true, true>(s, base) : launch_grid<true, false>(s, base));
-        else SDM_TRY(perm ? launch_grid<false, true>(s, base) : launch_grid<false, false>(s, base));
+        if (batched)
+            SDM_TRY(perm ? (launch_grid<true, true, false>(s, base)) : (launch_grid<true, false, false>(s, base)));
+        else
+            SDM_TRY(perm ? (launch_grid<false, true, false>(s, base)) : (launch_grid<false, false, false>(s, base)));
     }
     return SDM_OK;
 }

@@ -161,9 +161,11 @@ void plan_finish(Plan& plan);
 
 // Enqueue the wave-tier and grid-tier kernels for one step (base carries the
 // grid-tier arrays, see grid_args).
+// probe: instead of the collisions, the largest P_ij of every cell goes to
+// base.cell_max (single runs only; grid-tier entries must start at 0).
 sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* group_begin,
                        const uint32_t* group_end, uint32_t n_groups, const LaunchShape& shape,
-                       bool batched, bool perm);
+                       bool batched, bool perm, bool probe = false);
 
 bool shape_valid(const LaunchShape& sh);
 

@@ -83,6 +83,9 @@ struct StepArgs {
     // permutation-only mode outputs
     uint32_t* perm_out;
     uint32_t* nlive_out;
+    // probe mode output: largest P_ij per cell (grid-tier cells by atomic max on
+    // the bit pattern, so they must start at 0)
+    double* cell_max;
     uint32_t xcd_remap;
     // grid tier (cells spread over many workgroups)
     struct GridCell* gcell;
@@ -414,15 +417,22 @@ __device__ __forceinline__ void fetch_group(const StepArgs& a, uint64_t gi, uint
     }
 }
 
-template <int CAP, int WAVES, bool BATCHED, bool PERM, bool DRY = false>
+// PROBE: the same pairing, but instead of the collisions the largest P_ij of
+// every cell goes to a.cell_max (no uniforms drawn, nothing written back).
+template <int CAP, int WAVES, bool BATCHED, bool PERM, bool DRY = false, bool PROBE = false>
 __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
 {
     using Lds = GroupLds<CAP>;
     constexpr int K = CAP / kWave;   // storage slots per lane
+    static_assert(!PROBE || (!BATCHED && !PERM && !DRY), "probe of a single run");
+    static_assert(sizeof(CollEntry) * kQueueCap >= 8u * kGroupMaxCells, "probe maxima in the queue");
     __shared__ Lds lds_all[WAVES];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = threadIdx.x / kWave;
     Lds& L = lds_all[wv];
+    // probe mode: per-cell maxima (bit patterns of non-negative doubles) in the
+    // otherwise unused collision queue
+    unsigned long long* pmax = reinterpret_cast<unsigned long long*>(L.queue);
     const unsigned long long lanes_lt = (1ull << lane) - 1ull;
 
     const uint32_t blk = a.xcd_remap ? xcd_contiguous_block(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -492,8 +502,12 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
             L.dV[lane] = a.dV[c0 + lane];
             L.scale[lane] = nl >= 2 ? upscale_factor(nl) : 0.0;
             if constexpr (PERM) a.nlive_out[c0 + lane] = nl;
+            if constexpr (PROBE) pmax[lane] = 0ull;
         }
         if (n_tot == 0 || (!PERM && q_tot == 0)) {
+            if constexpr (PROBE) {
+                if (has_cell) a.cell_max[c0 + lane] = 0.0;
+            }
             wave_sync();
             if (g + 1 < g_end) fetch_group<K, PERM>(a, g + 1, lane, R);
             continue;
@@ -638,7 +652,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
         if constexpr (PERM) continue;
 
         // (4) uniform deviates, two pairs per Philox call
-        for (uint32_t i = lane; i < u_tot; i += kWave) {
+        for (uint32_t i = lane; !PROBE && i < u_tot; i += kWave) {
             const uint32_t uc = L.pairs.ucall[i];
             const uint32_t q = uc & 511u;
             const uint32_t c = (uc >> 9) & 63u;
@@ -648,6 +662,24 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
             if (uc >> 23) L.pairs.u[q + 1] = uniform_open01(w.w[2], w.w[3]);
         }
         wave_sync();
+
+        if constexpr (PROBE) {
+            // (5') P_ij of every pair; the largest per cell
+            for (uint32_t q = lane; q < q_tot; q += kWave) {
+                const uint32_t pi = L.pairs.pairinfo[q];
+                const uint32_t p = pi & 1023u;
+                const uint32_t c = pi >> 10;
+                const uint64_t xa = L.pairs.xi[p], xb = L.pairs.xi[p + 1];
+                const double Kab = collection_kernel(job.kernel, job.kp, L.pairs.r[p], L.pairs.r[p + 1]);
+                const double prob =
+                    collision_probability(xa >= xb ? xa : xb, Kab, job.dt, L.dV[c], L.scale[c]);
+                atomicMax(&pmax[c], static_cast<unsigned long long>(__double_as_longlong(prob)));
+            }
+            wave_sync();
+            if (has_cell) a.cell_max[c0 + lane] = __longlong_as_double(static_cast<long long>(pmax[lane]));
+            wave_sync();   // the maxima are read before the next group clears them
+            continue;
+        }
 
         // (5) pair tests; colliding pairs go to the queue
         uint32_t coll = 0;
@@ -700,13 +732,13 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
             coll_acc += coll;
         }
     }
-    if constexpr (!PERM) {
+    if constexpr (!PERM && !PROBE) {
         if (q_count > 0) {
             wave_sync();
             flush_collisions<DRY>(a, L.queue, q_head, q_count, lane);
         }
     }
-    if constexpr (!BATCHED && !PERM) {
+    if constexpr (!BATCHED && !PERM && !PROBE) {
         if (lane == 0 && (pair_acc || coll_acc))
             add_counts(a, false, 0, static_cast<uint32_t>(wave_id), pair_acc, coll_acc);
     }
@@ -944,10 +976,11 @@ static __global__ __launch_bounds__(kGridBlock) void k_grid_bucket_sort(const St
 // Pair tests: each thread takes the two pairs of one uniform call.  The pair
 // chunks of a cell go to one XCD (consecutive list entries, XCD-contiguous
 // block mapping), so the random reads of its xi and r share that XCD's L2.
-template <bool BATCHED, bool PERM>
+template <bool BATCHED, bool PERM, bool PROBE = false>
 __global__ __launch_bounds__(kGridBlock) void k_grid_pairs(const StepArgs a)
 {
     __shared__ uint32_t s_red[kGridBlock / kWave];
+    __shared__ double s_max[kGridBlock / kWave];
     const uint2 ch = a.gpchunk[xcd_contiguous_block(blockIdx.x, gridDim.x)];
     const GridCell& gc = a.gcell[ch.x];
     const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
@@ -965,6 +998,29 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_pairs(const StepArgs a)
     }
     const uint32_t npairs = n >> 1;
     const double scale = npairs ? upscale_factor(n) : 0.0;
+    if constexpr (PROBE) {
+        // largest P_ij of the chunk's pairs, then one atomic max per workgroup
+        double best = 0.0;
+        const uint32_t m_end = min(ch.y + kGridPairChunk, npairs);
+        for (uint32_t m = ch.y + threadIdx.x; m < m_end; m += kGridBlock) {
+            const uint32_t sa = a.scr_pos[j.off + 2 * m], sb = a.scr_pos[j.off + 2 * m + 1];
+            const uint64_t xa = a.xi[j.off + sa], xb = a.xi[j.off + sb];
+            const double K = collection_kernel(j.kernel, j.kp, a.r[j.off + sa], a.r[j.off + sb]);
+            best = fmax(best, collision_probability(xa >= xb ? xa : xb, K, j.dt, j.dV, scale));
+        }
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) best = fmax(best, __shfl_xor(best, d, kWave));
+        if ((threadIdx.x & (kWave - 1)) == 0) s_max[threadIdx.x / kWave] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double b = s_max[0];
+            for (int w = 1; w < kGridBlock / kWave; ++w) b = fmax(b, s_max[w]);
+            if (b > 0.0)
+                atomicMax(reinterpret_cast<unsigned long long*>(a.cell_max + gc.cell),
+                          static_cast<unsigned long long>(__double_as_longlong(b)));
+        }
+        return;
+    }
     uint32_t coll = 0;
     const uint32_t h_end = (min(ch.y + kGridPairChunk, npairs) + 1u) / 2u;
     for (uint32_t h = ch.y / 2u + threadIdx.x; h < h_end; h += kGridBlock) {
