@@ -639,7 +639,7 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
     const LaunchShape original = x->shape;
     std::vector<LaunchShape> cands;
     for (uint32_t slots : {256u, 512u})
-        for (uint32_t gpw : {1u, 2u, 4u, 8u})
+        for (uint32_t gpw : {1u, 2u, 4u, 8u, 12u, 16u})
             for (uint32_t wpb : {1u, 2u, 4u})
                 for (uint32_t xr : {0u, 1u}) {
                     LaunchShape c = original;

@@ -157,7 +157,7 @@ def test_full_size_domain(sdm_mod, oracle_mod):
     pop = synth.large_domain(seed=synth.SEEDS[0])
     kind = oracle_mod.GOLOVIN if pop.kernel == "golovin" else oracle_mod.GEOMETRIC
     ctx, ref = _pair(sdm_mod, oracle_mod, pop)
-    ctx.set_launch_config(group_slots=256, groups_per_wave=8, waves_per_block=1)   # as benchmarked
+    ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=3)   # as bench.py selects it
     assert _bits_equal(ctx.moments(3).cpu().numpy(), ref.moments(3))
     assert np.array_equal(ctx.sd_conc().cpu().numpy().astype(np.uint32), ref.sd_conc())
     g = ctx.probe(pop.dt, pop.kernel, pop.seed, 0)

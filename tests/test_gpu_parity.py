@@ -243,12 +243,12 @@ def test_large_domain_reduced_full_parity(sdm_mod, oracle_mod):
 
 def test_large_domain_full_size_sampled_cells(sdm_mod, oracle_mod):
     """1024 x 1024 cells (~134M SDs) in the launch configuration the benchmark's
-    autotuner selects on MI355X (256-slot groups, 8 per wavefront); the
+    autotuner selects on the state, as bench.py does; the
     oracle advances 2048 sampled cells (plus every injected empty/single cell kind)
     one by one with their own RNG cell index."""
     pop = synth.large_domain(seed=synth.SEEDS[0])
     ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV)
-    ctx.set_launch_config(group_slots=256, groups_per_wave=8, waves_per_block=1)   # as benchmarked
+    ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=3)   # as bench.py selects it
     cnt = np.bincount(pop.cell, minlength=pop.n_cells)
     off = np.concatenate([[0], np.cumsum(cnt)])
     g = np.random.default_rng(5)

@@ -159,7 +159,7 @@ def test_large_domain_release_rules_sampled_cells(sdm_mod, oracle_mod):
     advances 1024 sampled cells one by one with their own RNG cell index."""
     pop = synth.large_domain(seed=synth.SEEDS[1])
     ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV)
-    ctx.set_launch_config(group_slots=256, groups_per_wave=8, waves_per_block=1)   # as benchmarked
+    ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=3)   # as bench.py selects it
     rules = oracle_mod.RULE_FIDELITY | oracle_mod.RULE_RECYCLE
     ctx.set_rules(rules)
     cnt = np.bincount(pop.cell, minlength=pop.n_cells)
