@@ -19,7 +19,9 @@
  *     r_j and loses gamma*xi_k; when that would empty j, both SDs take the
  *     merged radius and share xi_k as floor(xi_k/2) (j) and the rest (k).
  *     (sdm_set_rules selects the paper's own rules instead: one event when
- *     u < p, a zero multiplicity on equal xi, and recycling.)
+ *     u < p, a zero multiplicity on equal xi, and recycling; sdm_dry_attach
+ *     adds the optional dry attributes r_d^3 and kappa, summed and averaged
+ *     into the merged droplets.)
  *
  * Randomness is counter-based Philox4x32-10 keyed by (seed, step, cell, slot)
  * (the paper's release uses Mersenne Twister, Sect. 5.3): the shuffle key of
