@@ -52,7 +52,7 @@ CtxLayout layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t c)
     L.err = cv.take<unsigned int>(64);
     L.probe_order = cv.take<uint32_t>(n);
     L.probe_cell = cv.take<double>(c);
-    L.probe_max = cv.take<unsigned long long>(32);
+    L.probe_max = cv.take<unsigned long long>(uint64_t(kMaxSlots) * kMaxStride);
     // the scratch region is shared by the step scratch and the init sort
     const uintptr_t scratch_begin = cv.cur;
     L.scr_kv = cv.take<uint64_t>(n);
@@ -261,9 +261,18 @@ static sdm_status step_args(sdm_ctx* x, double dt, sdm_kernel kernel, uint64_t s
 static sdm_status enqueue_recycle(sdm_ctx* x)
 {
     if (x->n_cells == 0) return SDM_OK;
+    // the per-cell pair counts borrow the probe's per-cell scratch (8 bytes a cell)
+    uint32_t* pairs = reinterpret_cast<uint32_t*>(x->probe_cell);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(x->n_cells, 256, 8192)), dim3(256), 0, x->stream,
+                       pairs, uint64_t(x->n_cells), 0u);
+    SDM_LAUNCHED();
     hipLaunchKernelGGL(k_recycle, dim3(grid_for(x->n_cells, kRecycleCellsPerBlock, 1u << 16)),
                        dim3(kRecycleBlock), 0, x->stream, x->offsets, x->xi, x->r, x->n_cells,
-                       x->probe_order, x->stats + kRecycledStat, x->rd3, x->kappa);
+                       x->probe_order, pairs, x->stats, x->rd3, x->kappa);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL(k_recycle_copy, dim3(grid_for(x->n_cells, 256, 8192)), dim3(256), 0,
+                       x->stream, x->offsets, pairs, x->probe_order, x->n_cells, x->r, x->rd3,
+                       x->kappa);
     SDM_LAUNCHED();
     return SDM_OK;
 }
@@ -365,8 +374,8 @@ static sdm_status enqueue_probe(sdm_ctx* x, double dt, sdm_kernel kernel, uint64
 {
     StepArgs a;
     SDM_TRY(step_args(x, dt, kernel, seed, step, &a));
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, x->stream, x->probe_max, uint64_t(1),
-                       0ull);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, x->stream, x->probe_max,
+                       uint64_t(kMaxSlots) * kMaxStride, 0ull);
     SDM_LAUNCHED();
     if (x->n_cells == 0) return SDM_OK;
     double* cm = cell_max ? cell_max : x->probe_cell;
@@ -387,9 +396,11 @@ static sdm_status enqueue_probe(sdm_ctx* x, double dt, sdm_kernel kernel, uint64
 
 static sdm_status read_probe_max(sdm_ctx* x, double* out)
 {
-    unsigned long long bits = 0;
-    SDM_HIP(hipMemcpyAsync(&bits, x->probe_max, sizeof(bits), hipMemcpyDeviceToHost, x->stream));
+    unsigned long long h[kMaxSlots * kMaxStride];
+    SDM_HIP(hipMemcpyAsync(h, x->probe_max, sizeof(h), hipMemcpyDeviceToHost, x->stream));
     SDM_HIP(hipStreamSynchronize(x->stream));
+    unsigned long long bits = 0;   // bit patterns of non-negative doubles order like the values
+    for (uint32_t i = 0; i < kMaxSlots; ++i) bits = std::max(bits, h[i * kMaxStride]);
     double v;
     std::memcpy(&v, &bits, sizeof(v));
     *out = v;
@@ -499,10 +510,13 @@ extern "C" sdm_status sdm_get_recycled(sdm_ctx* x, uint64_t* total)
         set_error("total is NULL");
         return SDM_EINVAL;
     }
-    unsigned long long v = 0;
-    SDM_HIP(hipMemcpyAsync(&v, x->stats + kRecycledStat, sizeof(v), hipMemcpyDeviceToHost,
-                           x->stream));
+    // the recycled-slot word of every counter slot
+    std::vector<unsigned long long> h(uint64_t(kStatSlots) * kStatStride);
+    SDM_HIP(hipMemcpyAsync(h.data(), x->stats, h.size() * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, x->stream));
     SDM_HIP(hipStreamSynchronize(x->stream));
+    uint64_t v = 0;
+    for (int i = 0; i < kStatSlots; ++i) v += h[uint64_t(i) * kStatStride + kRecycledStat];
     *total = v;
     return SDM_OK;
 }

@@ -108,8 +108,14 @@ __global__ __launch_bounds__(kDiagBlock) void k_sd_conc(const uint32_t* __restri
     }
 }
 
-// *gmax = max(*gmax, max of v[0, n)) for non-negative doubles, as the bit
-// pattern (which orders like the value); one atomic per workgroup.
+// Slots of the running maximum of k_max_reduce, kMaxStride words apart (one
+// 128-byte line each, so that the workgroups' atomics spread over lines).
+constexpr uint32_t kMaxSlots = 16;
+constexpr uint32_t kMaxStride = 16;
+
+// max over the slots gmax[s * kMaxStride] = max(those, max of v[0, n)) for
+// non-negative doubles, as the bit pattern (which orders like the value); one
+// atomic per workgroup, on slot blockIdx % kMaxSlots.
 __global__ __launch_bounds__(kDiagBlock) void k_max_reduce(const double* __restrict__ v, uint32_t n,
                                                           unsigned long long* __restrict__ gmax)
 {
@@ -125,7 +131,9 @@ __global__ __launch_bounds__(kDiagBlock) void k_max_reduce(const double* __restr
     if (threadIdx.x == 0) {
         double b = s_best[0];
         for (uint32_t w = 1; w < kDiagCellsPerBlock; ++w) b = fmax(b, s_best[w]);
-        if (b > 0.0) atomicMax(gmax, static_cast<unsigned long long>(__double_as_longlong(b)));
+        if (b > 0.0)
+            atomicMax(gmax + (blockIdx.x % kMaxSlots) * kMaxStride,
+                      static_cast<unsigned long long>(__double_as_longlong(b)));
     }
 }
 

@@ -33,8 +33,8 @@ constexpr int kStatStride = 16;                    // 128 bytes between counter 
 
 // Outcome rules of a step (bit flags, as the public rule flags).
 enum : uint32_t { kRuleRelease = 1u, kRuleRecycle = 2u };
-// Index of the recycled-slot counter in the single-run counter array (a free
-// word of the first counter slot).
+// Index of the recycled-slot counter within each slot of the single-run counter
+// array (a free word of every counter slot; the total is their sum).
 constexpr int kRecycledStat = 2;
 
 // Per-instance record of a batch (device table).

@@ -100,6 +100,25 @@ def test_explicit_recycle(sdm_mod, oracle_mod, max_per_cell, n_cells, dead):
     assert ctx.recycled() == n_ref + n_ref2
 
 
+@pytest.mark.parametrize("max_per_cell,n_cells", [(250, 300), (600, 60)])
+@pytest.mark.parametrize("dead", [0.02, 0.45])
+def test_explicit_recycle_distinct_multiplicities(sdm_mod, oracle_mod, max_per_cell, n_cells,
+                                                  dead):
+    # multiplicities up to 2^40, nearly all distinct: with many dead slots the
+    # threshold lies past the first few distinct values (the bit search); cells
+    # of up to 250 slots exchange in LDS, cells of up to 600 through the list
+    pop = synth.tiny_cells(seed=int(700 + max_per_cell + 100 * dead), n_cells=n_cells,
+                           max_per_cell=max_per_cell, xi_max=1 << 40, dead_fraction=dead)
+    ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV)
+    ref = oracle_mod.SlotState(pop.cell, pop.xi, pop.r, pop.dV)
+    for _ in range(2):
+        ctx.recycle()
+        _recycle_ref(oracle_mod, ref)
+        xi_g, r_g = ctx.state_numpy()
+        xi_o, r_o = ref.input_order()
+        assert np.array_equal(xi_g, xi_o) and _bits_equal(r_g, r_o)
+
+
 def test_recycle_edge_cells(sdm_mod, oracle_mod):
     # cell 0: all dead; cell 1: donors of multiplicity one; cell 2: ties; cell 3: empty;
     # cell 4: single dead slot among many live; cell 5: more dead than live
