@@ -326,7 +326,7 @@ static uint32_t substep_count(double pmax, double p_limit, uint32_t max_substeps
 // so that every cell's loads are in flight at once.
 static uint32_t diag_grid(uint32_t n_cells)
 {
-    return grid_for(n_cells, kDiagCellsPerBlock, 1u << 20);
+    return grid_for(n_cells, kDiagCellsPerBlock, kDiagMaxBlocks);
 }
 
 extern "C" sdm_status sdm_diag_sd_conc(sdm_ctx* x, uint32_t* out)

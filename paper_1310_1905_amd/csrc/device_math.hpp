@@ -174,6 +174,19 @@ __device__ inline double cbrt_rn(double x)
     return y;
 }
 
+// Remap the hardware workgroup id so that each XCD (workgroups are dealt to
+// the 8 XCDs round-robin) works on one contiguous range of logical blocks;
+// neighbouring cells then share cache lines in the same L2.
+__device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t bid, uint32_t nblk)
+{
+    constexpr uint32_t kXcds = 8;
+    const uint32_t xcd = bid % kXcds;
+    const uint32_t idx = bid / kXcds;
+    const uint32_t per = nblk / kXcds;
+    const uint32_t extra = nblk % kXcds;
+    return xcd * per + (xcd < extra ? xcd : extra) + idx;
+}
+
 // ---------------------------------------------------------------------------
 // Collection kernels
 // ---------------------------------------------------------------------------

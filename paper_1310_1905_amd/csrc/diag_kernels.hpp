@@ -21,6 +21,9 @@ namespace {
 constexpr int kDiagBlock = 256;
 constexpr uint32_t kMaxMomentOrder = 16;
 constexpr uint32_t kDiagCellsPerBlock = kDiagBlock / 64;
+// grid cap of the per-cell kernels: a few cells per wavefront (grid-stride)
+// rather than one wavefront launched per cell
+constexpr uint32_t kDiagMaxBlocks = 1u << 16;
 
 __device__ __forceinline__ double wave_fold_sum(double v, uint32_t lane)
 {
@@ -53,7 +56,8 @@ __global__ __launch_bounds__(kDiagBlock) void k_moments(const uint32_t* __restri
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kDiagCellsPerBlock;
-    for (uint64_t c = static_cast<uint64_t>(blockIdx.x) * kDiagCellsPerBlock + threadIdx.x / 64u;
+    const uint32_t blk = xcd_contiguous_block(blockIdx.x, gridDim.x);   // out lines per XCD
+    for (uint64_t c = static_cast<uint64_t>(blk) * kDiagCellsPerBlock + threadIdx.x / 64u;
          c < n_cells; c += stride) {
         const uint32_t b = off[c], n = off[c + 1] - b;
         double acc = 0.0;
@@ -90,7 +94,8 @@ __global__ __launch_bounds__(kDiagBlock) void k_sd_conc(const uint32_t* __restri
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kDiagCellsPerBlock;
-    for (uint64_t c = static_cast<uint64_t>(blockIdx.x) * kDiagCellsPerBlock + threadIdx.x / 64u;
+    const uint32_t blk = xcd_contiguous_block(blockIdx.x, gridDim.x);   // out lines per XCD
+    for (uint64_t c = static_cast<uint64_t>(blk) * kDiagCellsPerBlock + threadIdx.x / 64u;
          c < n_cells; c += stride) {
         const uint32_t b = off[c], n = off[c + 1] - b;
         uint32_t cnt = 0;

@@ -158,7 +158,7 @@ extern "C" sdm_status sdm_diag_dry_moments(sdm_ctx* x, uint32_t k, double rd_min
         set_error("out must be non-NULL");
         return SDM_EINVAL;
     }
-    hipLaunchKernelGGL(k_moments<true>, dim3(grid_for(x->n_cells, kDiagCellsPerBlock, 1u << 20)),
+    hipLaunchKernelGGL(k_moments<true>, dim3(grid_for(x->n_cells, kDiagCellsPerBlock, kDiagMaxBlocks)),
                        dim3(kDiagBlock), 0, x->stream, x->offsets, x->dV, x->xi, x->rd3,
                        x->n_cells, k, rd_min, rd_max, rho_d, out);
     SDM_LAUNCHED();

@@ -156,19 +156,6 @@ __device__ __forceinline__ CellJob resolve_cell(const StepArgs& a, uint32_t c)
     return j;
 }
 
-// Remap the hardware workgroup id so that each XCD (workgroups are dealt to
-// the 8 XCDs round-robin) works on one contiguous range of logical blocks;
-// neighbouring cells then share cache lines in the same L2.
-__device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t bid, uint32_t nblk)
-{
-    constexpr uint32_t kXcds = 8;
-    const uint32_t xcd = bid % kXcds;
-    const uint32_t idx = bid / kXcds;
-    const uint32_t per = nblk / kXcds;
-    const uint32_t extra = nblk % kXcds;
-    return xcd * per + (xcd < extra ? xcd : extra) + idx;
-}
-
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
