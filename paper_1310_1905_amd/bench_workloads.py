@@ -164,6 +164,7 @@ def run_transport(args):
     co = []
     t0 = time.perf_counter()
     for i in range(args.steps):
+        stream.synchronize()   # the previous coalescence step is not part of the transport time
         a = time.perf_counter()
         ctx.transport(cx_t, cz_t, pop.dt, sediment=True)   # synchronises (re-plan)
         b = time.perf_counter()
