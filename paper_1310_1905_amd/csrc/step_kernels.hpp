@@ -776,21 +776,75 @@ constexpr uint32_t kGridSubLg = 10;       // at most 2^10 sub-buckets per bucket
 // pairs per pair chunk: small, so that the chunks running at once on one XCD
 // cover few cells and their xi and r stay in that XCD's L2
 constexpr uint32_t kGridPairChunk = 512;
+// placement through LDS: chunks of kGridChunk slots with at most this many digits
+// (cells of up to 2^20 slots have at most 2^10)
+constexpr uint32_t kGridStagedDigits = 1024;
 
 // Digit counts (PLACE = false) or placement (PLACE = true) of one slot chunk.
-// Placement starts each digit's cursor at the chunk's scanned table entry; the
-// order within a (digit, chunk) run is arrival order and does not matter, the
-// bucket sort orders it exactly.
+// The order within a (digit, chunk) run is arrival order and does not matter:
+// the bucket sort orders it exactly.  A chunk of at most kGridChunk slots is
+// placed through LDS: its words are first grouped by digit there (local runs at
+// the exclusive scan of the chunk's digit counts) and then copied out, so that
+// consecutive threads write consecutive words of a run instead of each word
+// being a memory request of its own.  Larger chunks place every word straight
+// at its digit's cursor.
 template <bool BATCHED, bool PLACE>
 __global__ __launch_bounds__(kGridBlock) void k_grid_digits(const StepArgs a)
 {
-    __shared__ uint32_t s_cnt[kGridMaxDigits];
+    // direct: kGridMaxDigits counters; staged: kGridStagedDigits counters, as many
+    // local cursors and the kGridChunk staged words, over the same bytes
+    constexpr uint32_t kRawWords = PLACE ? kGridStagedDigits + kGridChunk : kGridMaxDigits / 2;
+    static_assert(!PLACE || kRawWords >= kGridMaxDigits / 2, "direct counters fit the buffer");
+    __shared__ uint64_t s_raw[kRawWords];
+    __shared__ uint32_t s_red[kGridBlock / kWave];
     const uint2 ch = a.gchunk[blockIdx.x];
     const GridCell& gc = a.gcell[ch.x];
     const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
     const uint32_t cb = gc.cb, D = 1u << cb, ncol = gc.ncol, col = ch.y >> gc.lgc;
     uint32_t* tbl = a.scr_cnt + j.off;
-    for (uint32_t d = threadIdx.x; d < D; d += kGridBlock) s_cnt[d] = PLACE ? tbl[d * ncol + col] : 0u;
+    // uniform over the workgroup
+    const bool staged = PLACE && gc.lgc == kGridChunkLg && D <= kGridStagedDigits;
+    uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_raw);
+    uint32_t* s_loc = s_cnt + kGridStagedDigits;   // staged only
+    uint64_t* s_stage = s_raw + kGridStagedDigits;  // staged only (past both counter arrays)
+    uint32_t m_chunk = 0;                                   // staged: the chunk's live words
+    if (staged) {
+        // run (d, col) starts at tbl[i] and holds tbl[i + 1] - tbl[i] words,
+        // i = d ncol + col (entry nb is the sentinel); thread t scans a run of
+        // `per` digits, then the waves' totals
+        constexpr int W = kGridBlock / kWave;
+        const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+        const uint32_t per = (D + kGridBlock - 1) / kGridBlock;
+        const uint32_t d0 = min(threadIdx.x * per, D), d1 = min(d0 + per, D);
+        uint32_t run = 0;
+        for (uint32_t d = d0; d < d1; ++d) {
+            const uint32_t i = d * ncol + col;
+            const uint32_t g = tbl[i];
+            const uint32_t c = tbl[i + 1] - g;
+            s_cnt[d] = g;
+            s_loc[d] = c;
+            run += c;
+        }
+        const uint32_t incl = wave_inclusive_sum(run, lane);
+        if (lane == kWave - 1) s_red[wv] = incl;
+        __syncthreads();
+        uint32_t before = incl - run;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            before += static_cast<uint32_t>(w) < wv ? s_red[w] : 0u;
+            m_chunk += s_red[w];
+        }
+        // s_loc: local cursor from the run's local start; s_cnt: global start
+        // minus local start, so that local index + s_cnt is the global place
+        for (uint32_t d = d0; d < d1; ++d) {
+            const uint32_t c = s_loc[d];
+            s_loc[d] = before;
+            s_cnt[d] -= before;
+            before += c;
+        }
+    } else {
+        for (uint32_t d = threadIdx.x; d < D; d += kGridBlock) s_cnt[d] = PLACE ? tbl[d * ncol + col] : 0u;
+    }
     __syncthreads();
     const uint32_t s_end = min(ch.y + (1u << gc.lgc), j.n_slots);
     const uint32_t q_end = (s_end + 3u) / 4u;
@@ -805,14 +859,27 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_digits(const StepArgs a)
             if (!live[t]) continue;
             const uint32_t d = bucket_of(w.w[t], cb);
             if constexpr (PLACE) {
-                const uint32_t p = atomicAdd(&s_cnt[d], 1u);
-                a.scr_kv[j.off + p] = (static_cast<uint64_t>(w.w[t]) << 32) | (4 * q + t);
+                const uint64_t word = (static_cast<uint64_t>(w.w[t]) << 32) | (4 * q + t);
+                if (staged) {
+                    s_stage[atomicAdd(&s_loc[d], 1u)] = word;   // < m_chunk <= kGridChunk
+                } else {
+                    const uint32_t p = atomicAdd(&s_cnt[d], 1u);
+                    a.scr_kv[j.off + p] = word;
+                }
             } else {
                 atomicAdd(&s_cnt[d], 1u);
             }
         }
     }
-    if constexpr (!PLACE) {
+    if constexpr (PLACE) {
+        if (staged) {
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < m_chunk; i += kGridBlock) {
+                const uint64_t v = s_stage[i];
+                a.scr_kv[j.off + s_cnt[bucket_of(static_cast<uint32_t>(v >> 32), cb)] + i] = v;
+            }
+        }
+    } else {
         __syncthreads();
         for (uint32_t d = threadIdx.x; d < D; d += kGridBlock) tbl[d * ncol + col] = s_cnt[d];
     }
