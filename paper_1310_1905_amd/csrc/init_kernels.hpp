@@ -172,10 +172,17 @@ __global__ __launch_bounds__(kWave) void k_radix_count(const uint32_t* keys, uin
     for (uint32_t d = lane; d < kRadixDigits; d += kWave) hist[d] = 0;
     __syncthreads();
     const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kRadixTile;
-    for (uint32_t t = lane; t < kRadixTile; t += kWave) {
-        const uint64_t i = base + t;
-        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & (kRadixDigits - 1)], 1u);
+    // all of the lane's keys first (independent loads), then the histogram
+    constexpr uint32_t kPer = kRadixTile / kWave;
+    uint32_t kk[kPer];
+#pragma unroll
+    for (uint32_t t = 0; t < kPer; ++t) {
+        const uint64_t i = base + t * kWave + lane;
+        kk[t] = i < n ? keys[i] : 0u;
     }
+#pragma unroll
+    for (uint32_t t = 0; t < kPer; ++t)
+        if (base + t * kWave + lane < n) atomicAdd(&hist[(kk[t] >> shift) & (kRadixDigits - 1)], 1u);
     __syncthreads();
     for (uint32_t d = lane; d < kRadixDigits; d += kWave)
         counts[static_cast<uint64_t>(d) * n_tiles + blockIdx.x] = hist[d];
@@ -195,11 +202,22 @@ __global__ __launch_bounds__(kWave) void k_radix_scatter(const uint32_t* keys_in
     __syncthreads();
     const unsigned long long lt = (1ull << lane) - 1ull;
     const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kRadixTile;
-    for (uint32_t c = 0; c < kRadixTile; c += kWave) {
-        const uint64_t i = base + c + lane;
+    // all of the lane's keys and values first (independent loads), then the
+    // chunks in order
+    constexpr uint32_t kPer = kRadixTile / kWave;
+    uint32_t kk[kPer], vv[kPer];
+#pragma unroll
+    for (uint32_t t = 0; t < kPer; ++t) {
+        const uint64_t i = base + t * kWave + lane;
+        kk[t] = i < n ? keys_in[i] : 0u;
+        vv[t] = i < n ? vals_in[i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t t = 0; t < kPer; ++t) {
+        const uint64_t i = base + t * kWave + lane;
         const bool valid = i < n;
-        const uint32_t k = valid ? keys_in[i] : 0u;
-        const uint32_t v = valid ? vals_in[i] : 0u;
+        const uint32_t k = kk[t];
+        const uint32_t v = vv[t];
         const uint32_t d = (k >> shift) & (kRadixDigits - 1);
         unsigned long long same = __ballot(valid);
 #pragma unroll
