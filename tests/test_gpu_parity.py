@@ -121,17 +121,18 @@ def test_grid_tier_cells(sdm_mod, oracle_mod, kernel):
 
 def test_grid_tier_plan_transitions(sdm_mod, oracle_mod):
     """Grid cells at the sizes where the digit bits or the slot-chunk size of the
-    grid tier change (257, 1024/1025, 2048/2049, 4097, 65537 and 2^20 + 1 slots,
-    the last with 4096-slot chunks), with dead slots: pairing order and two steps
-    bit-exact."""
+    grid tier change (257, 1024/1025, 2048/2049, 4097, 65537, 700001 and 2^20 + 1
+    slots; 700001 has the most digits, 1024, that chunks placed through LDS take, and
+    a partial last chunk; 2^20 + 1 has 4096-slot chunks placed directly), with dead
+    slots: pairing order and two steps bit-exact."""
     g = np.random.default_rng(77)
-    sizes = [257, 1024, 1025, 2048, 2049, 4097, 65537, (1 << 20) + 1, 100]
+    sizes = [257, 1024, 1025, 2048, 2049, 4097, 65537, 700001, (1 << 20) + 1, 100]
     cell = np.repeat(np.arange(len(sizes), dtype=np.uint32), sizes)
     n = cell.size
     xi = g.integers(1, 40, n).astype(np.uint64)
     xi[g.random(n) < 0.05] = 0
     r = np.exp(g.uniform(np.log(5e-6), np.log(2e-3), n))
-    dV = np.array([1e-2, 1e-1, 1e-1, 1.0, 1.0, 1.0, 10.0, 1e3, 1e-3])
+    dV = np.array([1e-2, 1e-1, 1e-1, 1.0, 1.0, 1.0, 10.0, 5e2, 1e3, 1e-3])
     ctx = sdm_mod.Context(cell, xi, r, dV)
     ctx.set_launch_config(group_slots=256)
     assert ctx.plan()[1:] == (1, len(sizes) - 1)
@@ -145,7 +146,7 @@ def test_grid_tier_plan_transitions(sdm_mod, oracle_mod):
         assert np.array_equal(order[off[c]:off[c] + exp.size], exp), sizes[c]
     for t in range(2):
         ctx.step(2.0, "geometric", 9, t)
-        ref.step_parallel(2.0, oracle_mod.GEOMETRIC, 9, t, threads=9)
+        ref.step_parallel(2.0, oracle_mod.GEOMETRIC, 9, t, threads=10)
     _assert_same(ctx, ref, "grid plan transitions")
     assert ref.stats[1] > 0
 
