@@ -103,7 +103,13 @@ typedef struct sdm_ctx sdm_ctx;
 /* Bytes of device workspace sdm_init needs for n_sd SDs in n_cells cells. */
 size_t sdm_workspace_bytes(uint64_t n_sd, uint32_t n_cells);
 
-/* Create a context and copy the SDs into workspace-resident state.
+/* Create a context and copy the SDs into workspace-resident state.  The
+ * attributes taken are those of a computational particle in Sect. 5.1 that
+ * coalescence reads and changes (multiplicity N, here xi; the wet radius; the
+ * location, here the index of the grid cell that holds it), plus the volume dV
+ * of every grid cell that eq. (P_ij) divides by: the state the particle-based
+ * scheme's initialisation (particles_t::init, Sect. 5.2) sets up before the
+ * first step.
  *   stream     : hipStream_t (as void*) all work of the context runs on.
  *   workspace  : dev, >= sdm_workspace_bytes(n_sd, n_cells) bytes, 256-byte
  *                aligned; owned by the caller, must outlive the context.
@@ -133,12 +139,17 @@ sdm_status sdm_coalesce_step(sdm_ctx *ctx, double dt, sdm_kernel kernel, uint64_
                              uint64_t step);
 
 /* Copy the current state back in input order: xi_out (dev uint64[n_sd]) and
- * r_out (dev double[n_sd]), either may be NULL.  Synchronises the stream. */
+ * r_out (dev double[n_sd]), either may be NULL: the multiplicity and radius of
+ * every computational particle (Sect. 5.1 attribute list) after the steps so
+ * far.  A particle the outcome rules of Sect. 5.1.4 left empty reads xi = 0.
+ * Synchronises the stream.  Errors: SDM_EINVAL (ctx NULL), SDM_EDEVICE. */
 sdm_status sdm_get_state(sdm_ctx *ctx, uint64_t *xi_out, double *r_out);
 
-/* Totals since sdm_init: pair tests (sum over steps and cells of floor(n/2))
- * and collisions (pairs with gamma > 0).  host outputs, nullable.
- * Synchronises the stream. */
+/* Totals since sdm_init: pair tests, i.e. the floor(n/2) pairs examined per
+ * cell and step of which eq. (P_ij) speaks (n live particles), summed over
+ * cells and steps; and collisions, the examined pairs with at least one
+ * collision event (Sect. 5.1.4).  host outputs, nullable.
+ * Synchronises the stream.  Errors: SDM_EINVAL (ctx NULL), SDM_EDEVICE. */
 sdm_status sdm_get_stats(sdm_ctx *ctx, uint64_t *pair_tests, uint64_t *collisions);
 
 /* Storage-order views for diagnostics: slot offsets (dev uint32[n_cells+1])
@@ -147,7 +158,8 @@ sdm_status sdm_get_stats(sdm_ctx *ctx, uint64_t *pair_tests, uint64_t *collision
 sdm_status sdm_get_layout(sdm_ctx *ctx, const uint32_t **offsets, const uint32_t **input_index);
 
 /* Compute, without changing the state, the pairing order step `step` would
- * use: for each cell c, order_out[offsets[c] + i] (dev uint32[n_sd]) = local
+ * use: the random grouping into non-overlapping pairs of Sect. 5.1.4
+ * (consecutive entries 2m, 2m+1 form pair m).  For each cell c, order_out[offsets[c] + i] (dev uint32[n_sd]) = local
  * slot of the i-th live SD after the shuffle, i < n_live_out[c]
  * (dev uint32[n_cells]).  Slots of order_out past n_live are left unchanged.
  * Synchronises the stream. */
@@ -200,11 +212,11 @@ sdm_status sdm_diag_sd_conc(sdm_ctx *ctx, uint32_t *out);
  * the super-droplets of cell c with xi_i > 0 and r_min <= r_i <= r_max
  * (a closed range; r_min > r_max gives zeros).  rho_d (dev double[n_cells])
  * is the dry-air density; NULL means 1, i.e. moments per unit volume.
- * r_i^k is the product of k factors r_i taken left to right (k <= 16); the
- * sum runs in a fixed order: 64 partial sums, partial l taking the cell's
- * local slots l, l+64, ... in ascending order, then folded pairwise
- * (partial[l] += partial[l+d], d = 32, 16, ..., 1), so the result is
- * reproducible bit for bit.
+ * r_i^k is the product of k factors r_i taken left to right (k <= 16).
+ * The terms are added in a fixed wavefront-parallel order (64 strided partial
+ * sums folded pairwise), so a result is reproducible bit for bit; against the
+ * plain sum of the definition it differs by rounding only, at most
+ * (2n + 4) 2^-53 relative for a cell of n slots (all terms are >= 0).
  * Errors: SDM_EINVAL (k > 16, NaN bound, out NULL), SDM_EDEVICE. */
 sdm_status sdm_diag_moments(sdm_ctx *ctx, uint32_t k, double r_min, double r_max,
                             const double *rho_d, double *out);
@@ -354,9 +366,14 @@ sdm_status sdm_get_launch_config(sdm_ctx *ctx, sdm_launch_config *cfg);
 sdm_status sdm_set_launch_config(sdm_ctx *ctx, const sdm_launch_config *cfg);
 
 /* Time every launch configuration of a small candidate set on this context
- * (each candidate runs `reps` steps), keep the fastest, and restore the state
- * exactly as it was.  Needs sdm_autotune_workspace_bytes() extra bytes of
- * device scratch (caller-owned).  best_out (host, nullable) gets the choice. */
+ * (each candidate runs `reps` steps under the context's rules), keep the
+ * fastest, and restore the state exactly as it was: multiplicities, radii, the
+ * dry attributes when attached, and the counters.  Needs
+ * sdm_autotune_workspace_bytes() bytes of device scratch (caller-owned, 256-byte
+ * aligned; 16 B per SD, 32 B per SD with dry attributes attached, so attach
+ * them before asking for the size).  best_out (host, nullable) gets the choice.
+ * Synchronises.  Errors: SDM_ENOMEM (scratch too small or misaligned), and as
+ * sdm_coalesce_step. */
 size_t sdm_autotune_workspace_bytes(sdm_ctx *ctx);
 sdm_status sdm_autotune(sdm_ctx *ctx, void *scratch, size_t scratch_bytes, double dt,
                         sdm_kernel kernel, uint64_t seed, uint32_t reps,

@@ -622,25 +622,20 @@ int oracle_sort_by_cell(uint64_t n_sd, const uint32_t *cell, uint32_t n_cells,
 /* diag_wet_mom of Sect. 5.2): per cell, the number of live super-droplets   */
 /* and the k-th moment  M = (rho_d dV)^-1 sum_{r_i in [r_min, r_max]} N_i r_i^k */
 /* over live super-droplets.                                                */
-/* Summation order (fixed, so results are reproducible bit for bit): the    */
-/* cell's slots are dealt to 64 partial sums by slot index modulo 64, each   */
-/* summed in ascending slot order; the partials are then added pairwise,     */
-/* partial[l] += partial[l + d] for d = 32, 16, 8, 4, 2, 1.                  */
+/* The sum is the plain one of the definition, taken term by term in         */
+/* ascending slot order; r^k is the product of k factors r, left to right.  */
 /* ------------------------------------------------------------------------ */
 double oracle_moment_cell(uint32_t n_slots, const uint64_t *xi, const double *r, int k,
                           double r_min, double r_max, double rho_d, double dV)
 {
-    double part[64];
-    for (int l = 0; l < 64; ++l) part[l] = 0.0;
+    double sum = 0.0;
     for (uint32_t s = 0; s < n_slots; ++s) {
         if (xi[s] == 0 || !(r[s] >= r_min && r[s] <= r_max)) continue;
         double rk = 1.0;
         for (int i = 0; i < k; ++i) rk = rk * r[s];
-        part[s % 64u] = part[s % 64u] + (double)xi[s] * rk;
+        sum = sum + (double)xi[s] * rk;
     }
-    for (int d = 32; d >= 1; d /= 2)
-        for (int l = 0; l < d; ++l) part[l] = part[l] + part[l + d];
-    return part[0] / (rho_d * dV);
+    return sum / (rho_d * dV);
 }
 
 void oracle_moments(uint32_t n_cells, const uint64_t *offsets, const double *dV,

@@ -369,7 +369,16 @@ extern "C" sdm_status sdm_batch_add(sdm_batch* b, const sdm_instance_desc* d, in
     h.cell_sizes.resize(d->n_cells);
     for (uint32_t c = 0; c < d->n_cells; ++c) h.cell_sizes[c] = off[c + 1] - off[c];
     st = rebuild_lists(b);
-    if (st != SDM_OK) return st;
+    if (st != SDM_OK) {
+        // roll the admission back: the instance leaves no record, no pool range
+        // and no work-list entry behind, and the lists are those of before
+        h = HostInstance();
+        InstanceRec off{};
+        hipMemcpyAsync(b->L.inst + slot, &off, sizeof(off), hipMemcpyHostToDevice, s);
+        fail(st);
+        const sdm_status again = rebuild_lists(b);
+        return again != SDM_OK ? again : st;
+    }
     *handle_out = slot;
     return SDM_OK;
 }

@@ -623,6 +623,10 @@ extern "C" size_t sdm_autotune_workspace_bytes(sdm_ctx* x)
     cv.take<uint64_t>(x->n_sd);
     cv.take<double>(x->n_sd);
     cv.take<unsigned long long>(uint64_t(kStatSlots) * kStatStride);
+    if (x->rd3) {   // the dry attributes change in the candidate steps as well
+        cv.take<double>(x->n_sd);
+        cv.take<double>(x->n_sd);
+    }
     return cv.used();
 }
 
@@ -644,9 +648,15 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
     uint64_t* xi_save = cv.take<uint64_t>(x->n_sd);
     double* r_save = cv.take<double>(x->n_sd);
     unsigned long long* st_save = cv.take<unsigned long long>(uint64_t(kStatSlots) * kStatStride);
+    double* rd3_save = x->rd3 ? cv.take<double>(x->n_sd) : nullptr;
+    double* kappa_save = x->rd3 ? cv.take<double>(x->n_sd) : nullptr;
     hipStream_t s = x->stream;
     SDM_HIP(hipMemcpyAsync(xi_save, x->xi, x->n_sd * 8, hipMemcpyDeviceToDevice, s));
     SDM_HIP(hipMemcpyAsync(r_save, x->r, x->n_sd * 8, hipMemcpyDeviceToDevice, s));
+    if (x->rd3) {
+        SDM_HIP(hipMemcpyAsync(rd3_save, x->rd3, x->n_sd * 8, hipMemcpyDeviceToDevice, s));
+        SDM_HIP(hipMemcpyAsync(kappa_save, x->kappa, x->n_sd * 8, hipMemcpyDeviceToDevice, s));
+    }
     SDM_HIP(hipMemcpyAsync(st_save, x->stats, uint64_t(kStatSlots) * kStatStride * 8,
                            hipMemcpyDeviceToDevice, s));
 
@@ -688,6 +698,10 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
         // the state must be what it was before the candidate ran
         hipMemcpyAsync(x->xi, xi_save, x->n_sd * 8, hipMemcpyDeviceToDevice, s);
         hipMemcpyAsync(x->r, r_save, x->n_sd * 8, hipMemcpyDeviceToDevice, s);
+        if (x->rd3) {
+            hipMemcpyAsync(x->rd3, rd3_save, x->n_sd * 8, hipMemcpyDeviceToDevice, s);
+            hipMemcpyAsync(x->kappa, kappa_save, x->n_sd * 8, hipMemcpyDeviceToDevice, s);
+        }
     }
     hipMemcpyAsync(x->stats, st_save, uint64_t(kStatSlots) * kStatStride * 8,
                    hipMemcpyDeviceToDevice, s);

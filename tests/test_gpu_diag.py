@@ -1,9 +1,11 @@
 """Parity of the gridded diagnostics, the collision-probability probe and the
 sub-stepping entry points with the FP64 oracle, through the C ABI.
 
-Bar: super-droplet concentrations and sub-step counts exact; moments and
-probabilities bit-exact (both sides fix the summation order and evaluate eq.
-(P_ij) in the same order without contraction); states after fixed or adaptive
+Bar: super-droplet concentrations and sub-step counts exact; probabilities
+bit-exact (both sides evaluate eq. (P_ij) in the same order without
+contraction); moments within (2n + 4) 2^-53 relative of the oracle's plain
+in-order sum for a cell of n slots (the device adds in a wavefront-parallel
+order; see the moments_close fixture); states after fixed or adaptive
 sub-stepping bit-exact.  Cases span all three kernel tiers (cells of a few,
 hundreds and tens of thousands of storage slots), empty, single-SD and dead-SD
 cells, radius ranges hitting data values, dry-air density, and the large
@@ -43,7 +45,7 @@ CASES = [(60, 200), (600, 120), (40000, 3)]   # (max slots per cell, cells): wav
 
 
 @pytest.mark.parametrize("max_per_cell,n_cells", CASES)
-def test_sd_conc_and_moments(sdm_mod, oracle_mod, max_per_cell, n_cells):
+def test_sd_conc_and_moments(sdm_mod, oracle_mod, moments_close, max_per_cell, n_cells):
     pop = synth.tiny_cells(seed=900 + max_per_cell, n_cells=n_cells, max_per_cell=max_per_cell,
                            dead_fraction=0.2)
     ctx, ref = _pair(sdm_mod, oracle_mod, pop)
@@ -56,17 +58,17 @@ def test_sd_conc_and_moments(sdm_mod, oracle_mod, max_per_cell, n_cells):
                             (3, r_hi, r_lo, None), (16, 0.0, math.inf, None)]:
         got = ctx.moments(k, lo, hi, rho_d=dens).cpu().numpy()
         exp = ref.moments(k, lo, hi, rho_d=dens)
-        assert _bits_equal(got, exp), (k, lo, hi, dens is not None)
+        moments_close(got, exp, np.diff(ref.offsets))
 
 
-def test_moments_follow_the_state(sdm_mod, oracle_mod):
+def test_moments_follow_the_state(sdm_mod, oracle_mod, moments_close):
     pop = synth.tiny_cells(seed=77, n_cells=300, max_per_cell=300, xi_max=50)
     ctx, ref = _pair(sdm_mod, oracle_mod, pop, dV_scale=1e-4)
     for t in range(25):
         ctx.step(2.0, "geometric", pop.seed, t)
         ref.step(2.0, oracle_mod.GEOMETRIC, pop.seed, t)
     for k in (0, 3):
-        assert _bits_equal(ctx.moments(k).cpu().numpy(), ref.moments(k)), k
+        moments_close(ctx.moments(k).cpu().numpy(), ref.moments(k), np.diff(ref.offsets))
     assert np.array_equal(ctx.sd_conc().cpu().numpy().astype(np.uint32), ref.sd_conc())
 
 
@@ -152,13 +154,13 @@ def test_invalid_arguments(sdm_mod):
         ctx.probe(-1.0, "golovin", 1, 0)
 
 
-def test_full_size_domain(sdm_mod, oracle_mod):
+def test_full_size_domain(sdm_mod, oracle_mod, moments_close):
     """1024 x 1024 cells, ~134M SDs."""
     pop = synth.large_domain(seed=synth.SEEDS[0])
     kind = oracle_mod.GOLOVIN if pop.kernel == "golovin" else oracle_mod.GEOMETRIC
     ctx, ref = _pair(sdm_mod, oracle_mod, pop)
     ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=3)   # as bench.py selects it
-    assert _bits_equal(ctx.moments(3).cpu().numpy(), ref.moments(3))
+    moments_close(ctx.moments(3).cpu().numpy(), ref.moments(3), np.diff(ref.offsets))
     assert np.array_equal(ctx.sd_conc().cpu().numpy().astype(np.uint32), ref.sd_conc())
     g = ctx.probe(pop.dt, pop.kernel, pop.seed, 0)
     g_o = ref.max_probability(pop.dt, kind, pop.seed, 0)

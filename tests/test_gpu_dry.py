@@ -126,7 +126,7 @@ def test_dry_with_transport(sdm_mod, oracle_mod, dry_first):
     _assert_same(ctx, ref, f"transport, dry attached {'first' if dry_first else 'second'}")
 
 
-def test_dry_moments(sdm_mod, oracle_mod):
+def test_dry_moments(sdm_mod, oracle_mod, moments_close):
     pop = synth.tiny_cells(seed=44, n_cells=300, max_per_cell=700, xi_max=50)
     rd3, kappa = _dry_inputs(pop.n_sd, 44)
     ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV)
@@ -138,4 +138,32 @@ def test_dry_moments(sdm_mod, oracle_mod):
                           (6, 1e-7, 1e-6, rho)):
         g = ctx.dry_moments(k, lo, hi, rh).cpu().numpy()
         o = ref.dry_moments(k, lo, hi, rh)
-        assert np.array_equal(_bits(g), _bits(o)), k
+        moments_close(g, o, np.diff(ref.offsets))
+
+
+@pytest.mark.parametrize("max_per_cell,n_cells", [(60, 200), (600, 60)])
+def test_autotune_with_dry_attributes(sdm_mod, oracle_mod, max_per_cell, n_cells):
+    """The autotuner's candidate steps merge r_d^3 and kappa and recycle; it must
+    put them back, so a tuned context continues exactly as one never tuned."""
+    pop = synth.tiny_cells(seed=850 + max_per_cell, n_cells=n_cells, max_per_cell=max_per_cell,
+                           xi_max=8, dead_fraction=0.1)
+    rd3, kappa = _dry_inputs(pop.n_sd, 850 + max_per_cell)
+    dV = pop.dV * 1e-4
+    tuned = sdm_mod.Context(pop.cell, pop.xi, pop.r, dV)
+    plain = sdm_mod.Context(pop.cell, pop.xi, pop.r, dV)
+    ref = oracle_mod.SlotState(pop.cell, pop.xi, pop.r, dV)
+    ref.set_dry(rd3, kappa)
+    for c in (tuned, plain):
+        c.attach_dry(rd3, kappa)
+        c.set_rules(3)   # release rules + recycling
+    tuned.autotune(3.0, "geometric", seed=pop.seed ^ 0x77, reps=2)
+    a, b = (t.cpu().numpy() for t in tuned.dry())
+    assert np.array_equal(_bits(a), _bits(rd3)) and np.array_equal(_bits(b), _bits(kappa))
+    assert tuned.stats() == (0, 0)
+    for t in range(6):
+        for c in (tuned, plain):
+            c.step(3.0, "geometric", pop.seed, t)
+        ref.step(3.0, oracle_mod.GEOMETRIC, pop.seed, t, rules=3)
+    assert ref.stats[1] > 0
+    _assert_same(tuned, ref, "autotuned, dry attached")
+    _assert_same(plain, ref, "never tuned, dry attached")

@@ -41,8 +41,23 @@ def test_moments_match_compensated_sum(oracle_mod, k):
     _, st = _state(oracle_mod, seed=5)
     mk = st.moments(k)
     for c, (b, e) in enumerate(_cells(st)):
-        ref = math.fsum(float(x) * float(r) ** k for x, r in zip(st.xi[b:e], st.r[b:e])) / st.dV[c]
-        assert mk[c] == pytest.approx(ref, rel=1e-13, abs=0.0)
+        # r ** k as k products left to right, as the definition's r^k is formed
+        terms = []
+        for x, r in zip(st.xi[b:e], st.r[b:e]):
+            rk = 1.0
+            for _ in range(k):
+                rk = rk * float(r)
+            terms.append(float(x) * rk)
+        exact = math.fsum(terms)
+        # a plain left-to-right sum of n non-negative terms is within
+        # (n - 1) 2^-53 (1 + O(n 2^-53)) of the exact sum; the division adds 2^-53
+        n = e - b
+        assert mk[c] == pytest.approx(exact / st.dV[c], rel=(n + 2) * 2.0 ** -53, abs=0.0)
+        # and it is the sum taken in ascending slot order, term by term
+        run = 0.0
+        for t in terms:
+            run = run + t
+        assert mk[c] == run / st.dV[c]
 
 
 def test_radius_range_is_inclusive_brute_force(oracle_mod):
