@@ -32,6 +32,10 @@ GEOMETRIC = 1
 # zero-multiplicity particles at the start of each step.
 RULE_FIDELITY = 1
 RULE_RECYCLE = 2
+# Recycling over the whole domain: donors are the highest-multiplicity particles
+# of the domain and a recycled particle takes all of a donor's properties,
+# location included (so it joins the donor's cell); see SlotState.recycle_domain.
+RULE_RECYCLE_DOMAIN = 4
 
 # Default kernel parameters: Golovin b = 1500 s^-1; terminal velocity after
 # Rogers & Yau (1989) in SI units (k1 r^2 below 40 um, k2 r up to 600 um,
@@ -97,6 +101,8 @@ def lib() -> ctypes.CDLL:
     L.oracle_recycle_cell.restype = u32
     L.oracle_recycle_cell_dry.argtypes = [u32, P, P, P, P]
     L.oracle_recycle_cell_dry.restype = u32
+    L.oracle_recycle_domain.argtypes = [u32, P, P, P, P, P, P]
+    L.oracle_recycle_domain.restype = u32
     L.oracle_step_dry.argtypes = [u32, P, P, P, P, dbl, i32, P, u64, u32, u32, P, u32, P, P]
     L.oracle_step_dry.restype = i32
     L.oracle_dry_merge.argtypes = [u64, dbl, dbl, dbl, dbl, P, P]
@@ -268,9 +274,36 @@ class SlotState:
             return None, None
         return self.rd3[base:].ctypes.data, self.kappa[base:].ctypes.data
 
+    def recycle_domain(self) -> int:
+        """Recycling over the whole domain (the procedure of Sect. 5.1.4 with no
+        restriction to a cell): each recycled slot takes its donor's properties,
+        location included.  With positions attached the storage is then re-sorted
+        by the cells of the positions (stable in the old storage order); a state of
+        one cell needs no positions.  Returns the number of recycled slots."""
+        has_pos = hasattr(self, "x")
+        if self.n_cells > 1 and not has_pos:
+            raise ValueError("domain-wide recycling of several cells needs positions")
+        rd3_p = None if self.rd3 is None else _ptr(self.rd3)
+        kappa_p = None if self.rd3 is None else _ptr(self.kappa)
+        n = int(lib().oracle_recycle_domain(self.xi.size, _ptr(self.xi), _ptr(self.r), rd3_p,
+                                            kappa_p, _ptr(self.x) if has_pos else None,
+                                            _ptr(self.z) if has_pos else None))
+        self.recycled = getattr(self, "recycled", 0) + n
+        if has_pos and n > 0:
+            nx, nz, dx, dz = self.grid
+            i = np.clip(np.floor(self.x / dx), 0, nx - 1).astype(np.uint32)
+            k = np.clip(np.floor(self.z / dz), 0, nz - 1).astype(np.uint32)
+            self._resort(i + np.uint32(nx) * k)
+        return n
+
     def step(self, dt: float, kind: int, seed: int, step: int, params=None,
              cells: tuple | None = None, cell_index_base: int = 0, rules: int = 0):
-        """One coalescence step over all cells, or over the cell range ``cells``."""
+        """One coalescence step over all cells, or over the cell range ``cells``.
+        With RULE_RECYCLE_DOMAIN the domain-wide recycling runs first."""
+        if rules & RULE_RECYCLE_DOMAIN:
+            assert cells is None, "domain-wide recycling steps the whole domain"
+            self.recycle_domain()
+            rules &= ~RULE_RECYCLE_DOMAIN
         p = _params(params)
         c0, c1 = (0, self.n_cells) if cells is None else cells
         off = np.ascontiguousarray(self.offsets[c0:c1 + 1])
@@ -291,6 +324,9 @@ class SlotState:
     def step_parallel(self, dt, kind, seed, step, params=None, threads: int = 8, rules: int = 0):
         """Same result as ``step``: cells are independent, so ranges of cells run
         in separate threads (ctypes releases the GIL)."""
+        if rules & RULE_RECYCLE_DOMAIN:
+            self.recycle_domain()
+            rules &= ~RULE_RECYCLE_DOMAIN
         n = self.n_cells
         if threads <= 1 or n < 2 * threads:
             return self.step(dt, kind, seed, step, params, rules=rules)

@@ -425,17 +425,20 @@ static int cmp_u32(const void *pa, const void *pb)
     return a < b ? -1 : (a > b ? 1 : 0);
 }
 
-uint32_t oracle_recycle_cell_dry(uint32_t n_slots, uint64_t *xi, double *r, double *rd3,
-                                 double *kappa)
+/* The recycling procedure over one range of slots (a cell, or the whole
+ * domain).  x, z (nullable): positions, copied from the donor with its other
+ * properties (location is one of the particle attributes of Sect. 5.1). */
+static uint32_t recycle_range(uint32_t n_slots, uint64_t *xi, double *r, double *rd3,
+                              double *kappa, double *x, double *z)
 {
     uint32_t n = n_slots ? n_slots : 1u;
     uint32_t *dead = (uint32_t *)malloc(sizeof(uint32_t) * n);
     uint32_t *donor = (uint32_t *)malloc(sizeof(uint32_t) * n);
     ranked_slot *live = (ranked_slot *)malloc(sizeof(ranked_slot) * n);
-    uint32_t z = 0, L = 0;
+    uint32_t z_dead = 0, L = 0;
     for (uint32_t s = 0; s < n_slots; ++s) {
         if (xi[s] == 0) {
-            dead[z++] = s;
+            dead[z_dead++] = s;
         } else {
             live[L].xi = xi[s];
             live[L].slot = s;
@@ -443,9 +446,9 @@ uint32_t oracle_recycle_cell_dry(uint32_t n_slots, uint64_t *xi, double *r, doub
         }
     }
     uint32_t nd = 0;
-    if (z > 0 && L > 0) {
+    if (z_dead > 0 && L > 0) {
         qsort(live, L, sizeof(ranked_slot), cmp_ranked_slot);
-        uint32_t take = z < L ? z : L;
+        uint32_t take = z_dead < L ? z_dead : L;
         for (uint32_t i = 0; i < take; ++i)
             if (live[i].xi >= 2u) donor[nd++] = live[i].slot;
         qsort(donor, nd, sizeof(uint32_t), cmp_u32);
@@ -458,6 +461,10 @@ uint32_t oracle_recycle_cell_dry(uint32_t n_slots, uint64_t *xi, double *r, doub
                 rd3[t] = rd3[d];
                 kappa[t] = kappa[d];
             }
+            if (x) {
+                x[t] = x[d];
+                z[t] = z[d];
+            }
             xi[d] = xi[d] - half;
         }
     }
@@ -465,6 +472,25 @@ uint32_t oracle_recycle_cell_dry(uint32_t n_slots, uint64_t *xi, double *r, doub
     free(donor);
     free(live);
     return nd;
+}
+
+uint32_t oracle_recycle_cell_dry(uint32_t n_slots, uint64_t *xi, double *r, double *rd3,
+                                 double *kappa)
+{
+    return recycle_range(n_slots, xi, r, rd3, kappa, NULL, NULL);
+}
+
+/* Recycling over the whole domain (the same procedure, with no restriction to
+ * a cell): dead and live slots are taken over all n storage slots, the donors
+ * are the min(z, L) live slots of the domain ranked first by multiplicity
+ * (largest first, ties to the lower storage slot), and each recycled slot takes
+ * all of its donor's properties: radius, dry attributes, and its location (the
+ * positions x, z when given).  The caller re-sorts the storage by the cells of
+ * the new locations.  Returns the number of recycled slots. */
+uint32_t oracle_recycle_domain(uint32_t n, uint64_t *xi, double *r, double *rd3, double *kappa,
+                               double *x, double *z)
+{
+    return recycle_range(n, xi, r, rd3, kappa, x, z);
 }
 
 uint32_t oracle_recycle_cell(uint32_t n_slots, uint64_t *xi, double *r)
