@@ -9,7 +9,11 @@ collision update, all in one kernel launch for this cell-size range).
 
 Prints ONE JSON line: pair tests/s over the timed steps, the roofline of the
 dominant kernel (algorithmic bytes per launch / mean launch duration from HIP events
-on the launch stream), and the FP64 CPU oracle timed on a bounded sample.
+on the launch stream), and the FP64 CPU oracle timed on a bounded sample (all cores
+the process may use, and one thread).  The same line carries the other workloads'
+figures: us/step of the Golovin box and of the 2D domain, the batched ensemble
+against per-instance plain launches, and the served stream's p50/p99 latency
+against sequential plain launches (--headline-only skips them).
 
 Other workloads (--workload): domain2d, box, ensemble (batched vs per-instance plain
 launches), served (continuous batching vs sequential plain launches), transport
@@ -32,10 +36,11 @@ sys.path.insert(0, ROOT)
 METRIC = "coalescence pair tests/s + achieved HBM GB/s; served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes: read xi and r of every SD (16 B), offset (4 B) and volume (8 B)
-# of every cell, write the multiplicity of j and the radius of k per collision (16 B)
+# of every cell, write both members of a colliding pair (2 x 16 B; most collisions
+# change only xi_j and r_k, so this is the generous count)
 BYTES_PER_SD = 16
 BYTES_PER_CELL = 12
-BYTES_PER_COLLISION = 16
+BYTES_PER_COLLISION = 32
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_wave_groups_large_domain.txt")
 SQ_FILE = os.path.join(ROOT, "profiles", "sq_k_wave_groups_large_domain.txt")
 KERNEL_SOURCES = ["paper_1310_1905_amd/csrc/step_kernels.hpp",
@@ -85,23 +90,59 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pop, n_cells_sample: int, steps: int):
-    """The FP64 oracle on the first n_cells_sample cells for `steps` steps,
-    threads over independent cell ranges."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_cores() -> int:
+    """Cores this process may run on: its CPU affinity, capped by OMP_NUM_THREADS
+    when the host sets it (the share of the machine granted to the job)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def _oracle_rate(pop, n_cells_sample: int, steps: int, threads: int):
     import oracle
-    threads = min(16, os.cpu_count() or 1)
     ncs = min(n_cells_sample, pop.n_cells)
     n_sd = int(np.count_nonzero(pop.cell < ncs))
     st = oracle.SlotState(pop.cell[:n_sd], pop.xi[:n_sd], pop.r[:n_sd], pop.dV[:ncs])
     kind = oracle.GEOMETRIC if pop.kernel == "geometric" else oracle.GOLOVIN
     t0 = time.perf_counter()
     for t in range(steps):
-        st.step_parallel(pop.dt, kind, pop.seed, t, threads=threads)
+        if threads == 1:
+            st.step(pop.dt, kind, pop.seed, t)
+        else:
+            st.step_parallel(pop.dt, kind, pop.seed, t, threads=threads)
     el = time.perf_counter() - t0
-    return {"value": float(st.stats[0]) / el, "unit": "pair tests/s", "cores": threads,
-            "kind": "oracle",
+    return float(st.stats[0]) / el, ncs, n_sd, el
+
+
+def cpu_baseline(pop, n_cells_sample: int, steps: int, single_cells: int):
+    """The FP64 oracle as it stands, on all cores this process may use (threads
+    over independent cell ranges; bit-identical to one thread), and on one thread
+    over a smaller sample of the same domain."""
+    cores = _host_cores()
+    rate, ncs, n_sd, el = _oracle_rate(pop, n_cells_sample, steps, cores)
+    rate1, ncs1, n_sd1, el1 = _oracle_rate(pop, single_cells, 1, 1)
+    return {"value": rate, "unit": "pair tests/s", "cores": cores, "kind": "oracle",
             "sample": f"first {ncs} of {pop.n_cells} cells ({n_sd} SDs), {steps} steps, "
-                      f"{el:.1f} s wall on {threads} threads"}
+                      f"{el:.1f} s wall on {cores} threads",
+            "single_thread_value": rate1,
+            "single_thread_sample": f"first {ncs1} cells ({n_sd1} SDs), 1 step, {el1:.1f} s",
+            "cpu_model": _cpu_model(), "host_cpus_visible": os.cpu_count()}
 
 
 def bench_large(args):
@@ -176,7 +217,7 @@ def bench_large(args):
         del a, b
     if args.cpu_baseline:
         log("timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(pop, args.cpu_cells, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(pop, args.cpu_cells, args.cpu_steps, args.cpu_cells_1t)
     return out
 
 
@@ -193,9 +234,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-cells", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-cells-1t", type=int, default=1 << 17,
+                    help="cells of the single-thread oracle sample")
+    ap.add_argument("--headline-only", dest="others", action="store_false",
+                    help="skip the box, 2D-domain, ensemble and served figures of the "
+                         "default run")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0)
     ap.add_argument("--instances", type=int, default=4096, help="ensemble size")
-    ap.add_argument("--requests", type=int, default=48, help="served stream length")
+    ap.add_argument("--requests", type=int, default=200, help="served stream length")
+    ap.add_argument("--served-requests", type=int, default=200,
+                    help="served stream length of the headline run's served figures")
     ap.add_argument("--max-run", type=int, default=3600, help="longest served run (steps)")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="served HBM budget")
     ap.add_argument("--launch", default="",
@@ -209,6 +257,9 @@ def main():
         sys.exit(2)
     if args.workload == "large":
         out = bench_large(args)
+        if args.others:
+            from paper_1310_1905_amd import bench_workloads
+            out.update(bench_workloads.secondary(args))
     else:
         from paper_1310_1905_amd import bench_workloads
         out = bench_workloads.run(args)

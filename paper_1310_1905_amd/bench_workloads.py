@@ -42,6 +42,8 @@ def _line(args, value, ms_per_step, workload, extra=None, unit="pair tests/s"):
 def _single(args, pop, workload):
     stream = torch.cuda.Stream()
     ctx = sdm.Context(pop.cell, pop.xi, pop.r, pop.dV, stream=stream)
+    if getattr(args, "autotune", True):
+        ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=5)
     for t in range(args.warmup):
         ctx.step(pop.dt, pop.kernel, pop.seed, t)
     torch.cuda.synchronize()
@@ -52,8 +54,11 @@ def _single(args, pop, workload):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     p1, _ = ctx.stats()
+    cfg = ctx.launch_config().as_dict()
+    ctx.close()
     return _line(args, (p1 - p0) / wall, wall * 1e3 / args.steps, workload,
-                 {"n_sd": pop.n_sd, "n_cells": pop.n_cells, "us_per_step": wall * 1e6 / args.steps})
+                 {"n_sd": pop.n_sd, "n_cells": pop.n_cells, "us_per_step": wall * 1e6 / args.steps,
+                  "launch": cfg})
 
 
 def run_ensemble(args):
@@ -134,6 +139,7 @@ def run_served(args):
     seq_pairs = sum(r.pair_tests for r in seq)
     return _line(args, pairs / wall, None, "served_poisson_stream_continuous_batching",
                  {"requests": len(reqs), "arrival_rate_per_s": 1.0 / scale,
+                  "largest_request_sds": max(q.pop.n_sd for q in reqs),
                   "saturated_requests_per_s": sat_rate,
                   "latency": served, "sequential_latency": serve.latency_summary(seq),
                   "sequential_pair_tests_per_s": seq_pairs / wall_seq,
@@ -237,6 +243,56 @@ def run_extras(args):
                   "sd_conc_ms": conc_ms, "sd_conc_GBps": conc_bytes / (conc_ms * 1e-3) / 1e9,
                   "probe_ms": probe_ms},
                  unit="SDs/s (moment kernel)")
+
+
+def secondary(args):
+    """The figures of the other workloads for the headline line, each on its own
+    small budget of steps: us/step of the box and the 2D domain, the batched
+    ensemble against per-instance plain launches, the served stream's latency."""
+    import argparse
+    out = {}
+
+    def sub(**kw):
+        d = dict(vars(args))
+        d.update(kw)
+        return argparse.Namespace(**d)
+
+    log("box: 8192 SDs, Golovin")
+    box = _single(sub(steps=400, warmup=20), synth.box_golovin(seed=synth.SEEDS[0]),
+                  "box_8192_golovin")
+    out["box_us_per_step"] = box["config"]["us_per_step"]
+    log("2D domain: 75 x 75 x 64 SDs, geometric")
+    d2 = _single(sub(steps=400, warmup=20), synth.domain_2d(seed=synth.SEEDS[0]),
+                 "domain_2d_75x75x64_geometric")
+    out["domain2d_us_per_step"] = d2["config"]["us_per_step"]
+    out["box_launch"] = box["config"]["launch"]
+    out["domain2d_launch"] = d2["config"]["launch"]
+    log("ensemble: 4096 boxes")
+    ens = run_ensemble(sub(steps=30, warmup=3))
+    c = ens["config"]
+    out["ensemble"] = {"workload": c["workload"], "instances": c["instances"], "n_sd": c["n_sd"],
+                       "ms_per_batch_step": ens["ms_per_step"],
+                       "pair_tests_per_s": ens["value"],
+                       "plain_ms_per_step": c["plain_ms_per_step"],
+                       "plain_pair_tests_per_s": c["plain_launch_pair_tests_per_s"],
+                       "speedup_vs_plain": c["speedup_vs_plain"],
+                       "bit_identical_to_plain": c["bit_identical_to_plain"]}
+    torch.cuda.empty_cache()
+    log(f"served: {args.served_requests} requests")
+    srv = run_served(sub(requests=args.served_requests))
+    c = srv["config"]
+    out["served"] = {"workload": c["workload"], "requests": c["requests"],
+                     "largest_request_sds": c["largest_request_sds"],
+                     "arrival_rate_per_s": c["arrival_rate_per_s"],
+                     "load_vs_saturation": 0.7,
+                     "p50_s": c["latency"]["p50_s"], "p99_s": c["latency"]["p99_s"],
+                     "pair_tests_per_s": srv["value"],
+                     "sequential_p50_s": c["sequential_latency"]["p50_s"],
+                     "sequential_p99_s": c["sequential_latency"]["p99_s"],
+                     "sequential_pair_tests_per_s": c["sequential_pair_tests_per_s"],
+                     "speedup_vs_sequential": c["speedup_vs_sequential"],
+                     "saturated_pair_tests_per_s": c["saturated_pair_tests_per_s"]}
+    return out
 
 
 def run(args):
