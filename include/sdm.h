@@ -441,6 +441,45 @@ sdm_status sdm_batch_info(sdm_batch *b, uint32_t *n_instances, uint64_t *free_sd
 void sdm_batch_destroy(sdm_batch *b);
 
 /* ------------------------------------------------------------------------ */
+/* A step that allocates nothing, for callers that cannot allocate device    */
+/* memory or pass a workspace (code under stream capture set-up, serving     */
+/* loops with a fixed footprint).                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Size in bytes of the library's static device scratch (16 MiB; one copy per
+ * device, held until the process ends). */
+size_t sdm_static_scratch_bytes(void);
+
+/* One coalescence step, as sdm_coalesce_step with the default rules, of SDs
+ * that the caller already keeps sorted by cell: cell c owns the storage slots
+ * [offsets[c], offsets[c+1]) of xi and r, and the results are those of a
+ * context created by sdm_init from these arrays (cell index = the cell whose
+ * range holds the slot) after sdm_coalesce_step(ctx, dt, kernel, seed, step),
+ * bit for bit.  The launch plan, the counters and the flags live in the static
+ * scratch; the call allocates and frees no device memory.
+ *   stream   : hipStream_t (as void*) of the current device.
+ *   n_sd     : number of SDs, < 2^32; n_cells <= 2^20 cells, every cell with at
+ *              most 512 slots (larger cells need a context).
+ *   offsets  : dev uint32[n_cells + 1], offsets[0] = 0, non-decreasing,
+ *              offsets[n_cells] = n_sd.
+ *   xi, r    : dev uint64[n_sd], double[n_sd], updated in place (xi = 0 is a
+ *              dead SD; radii must be finite and > 0: they are not checked).
+ *   dV       : dev double[n_cells], finite and > 0.
+ *   params   : host, nullable (defaults).
+ *   pair_tests, collisions : host, nullable; this step's totals.
+ * Synchronises the stream (to read the launch plan's size, and the totals).
+ * Every call on a device shares that device's scratch, so calls that overlap
+ * on one device (other host threads, other streams) race: serialise them.
+ * Errors: SDM_EINVAL (more than 2^20 cells, a cell above 512 slots, bad
+ * offsets or volumes, dt, kernel, step >= 2^32, NULL arrays; nothing is
+ * changed), SDM_EDEVICE (a HIP failure). */
+sdm_status sdm_coalesce_sorted_static(void *stream, uint64_t n_sd, uint32_t n_cells,
+                                      const uint32_t *offsets, uint64_t *xi, double *r,
+                                      const double *dV, double dt, sdm_kernel kernel,
+                                      const sdm_kernel_params *params, uint64_t seed,
+                                      uint64_t step, uint64_t *pair_tests, uint64_t *collisions);
+
+/* ------------------------------------------------------------------------ */
 /* Element-wise checks of the device arithmetic (used by the parity tests).  */
 /* All arrays are dev, length n; the call synchronises the stream.           */
 /* ------------------------------------------------------------------------ */

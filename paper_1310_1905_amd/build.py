@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsdm.so")
-SOURCES = ["runtime.hip", "context.hip", "transport.hip", "dry.hip", "batch.hip", "debug.hip"]
+SOURCES = ["runtime.hip", "context.hip", "transport.hip", "dry.hip", "batch.hip", "debug.hip",
+           "static_step.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -32,14 +32,7 @@ struct TransportState {
     uint32_t* in_low = nullptr;     // incoming movers from lower cells, per cell
     uint32_t* count = nullptr;      // new slots per cell (n_cells + 1, last 0)
     uint32_t* tile_sums = nullptr;  // scan scratch
-    // launch plan on the device
-    uint8_t* jump = nullptr;        // cells of the greedy group a cell would open
-    uint8_t* exits = nullptr;       // chunk walk exits per entry
-    uint8_t* entries = nullptr;     // chunk walk entries
-    uint8_t* super_exits = nullptr; // exits of runs of chunk tables, per entry
-    uint8_t* super_entries = nullptr;
-    uint32_t* start = nullptr;      // group-start flags, then their prefix
-    uint32_t* plan_info = nullptr;  // [0] large-cell flag, [1] plan check flag
+    DevicePlanArrays plan;          // launch plan on the device
 };
 
 }  // namespace sdm

@@ -1,6 +1,7 @@
 // runtime.hip -- shared host runtime: errors, scan/sort launches and the
 // dispatch of the step kernels over launch shapes.
 #include "runtime.hpp"
+#include "plan_kernels.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -379,6 +380,78 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
         else
             SDM_TRY(perm ? (launch_grid<false, true, false>(s, base)) : (launch_grid<false, false, false>(s, base)));
     }
+    return SDM_OK;
+}
+
+void carve_device_plan(Carver& c, uint32_t nc, DevicePlanArrays* p)
+{
+    const uint64_t chunks = (uint64_t(nc) + kPlanChunk - 1) / kPlanChunk + 1;
+    const uint64_t supers = (chunks + kPlanSuper - 1) / kPlanSuper;
+    p->jump = c.take<uint8_t>(uint64_t(nc) + 1);
+    p->exits = c.take<uint8_t>(chunks * kGroupMaxCells);
+    p->entries = c.take<uint8_t>(chunks);
+    p->super_exits = c.take<uint8_t>(supers * kGroupMaxCells);
+    p->super_entries = c.take<uint8_t>(supers);
+    p->start = c.take<uint32_t>(uint64_t(nc) + 1);
+    p->info = c.take<uint32_t>(64);
+    p->tile_sums = c.take<uint32_t>((uint64_t(nc) + 1 + kScanTile - 1) / kScanTile + 2);
+}
+
+sdm_status device_plan(hipStream_t st, uint32_t nc, const uint32_t* offsets, uint32_t cap,
+                       const DevicePlanArrays& P, uint32_t* group_begin, uint32_t* group_end,
+                       uint32_t* n_groups, bool* usable, bool* big)
+{
+    *usable = false;
+    *big = false;
+    *n_groups = 0;
+    if (nc == 0) {
+        *usable = true;
+        return SDM_OK;
+    }
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, P.info, uint64_t(4), 0u);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL(k_plan_jump, dim3(grid_for(nc, 256, 8192)), dim3(256), 0, st, nc, offsets,
+                       cap, P.jump, P.info);
+    SDM_LAUNCHED();
+    const uint32_t chunks = (nc + kPlanChunk - 1) / kPlanChunk;
+    hipLaunchKernelGGL(k_plan_chunks, dim3(chunks), dim3(kGroupMaxCells), 0, st, nc, P.jump,
+                       P.exits);
+    SDM_LAUNCHED();
+    const uint32_t supers = (chunks + kPlanSuper - 1) / kPlanSuper;
+    hipLaunchKernelGGL(k_plan_super, dim3(supers), dim3(kGroupMaxCells), 0, st, chunks, P.exits,
+                       P.super_exits);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL(k_plan_stitch, dim3(1), dim3(1), 0, st, supers, P.super_exits,
+                       P.super_entries);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL(k_plan_entries, dim3(supers), dim3(kGroupMaxCells), 0, st, chunks, P.exits,
+                       P.super_entries, P.entries);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL(k_plan_mark, dim3(chunks), dim3(256), 0, st, nc, P.jump, P.entries, P.start);
+    SDM_LAUNCHED();
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, P.start + nc, uint64_t(1), 0u);
+    SDM_LAUNCHED();
+    SDM_TRY(scan_exclusive(st, P.start, P.start, uint64_t(nc) + 1, P.tile_sums));
+    hipLaunchKernelGGL(k_plan_emit, dim3(grid_for(nc, 256, 8192)), dim3(256), 0, st, nc, P.start,
+                       P.jump, group_begin, group_end);
+    SDM_LAUNCHED();
+    uint32_t info[2] = {0, 0};   // large-cell flag, group count
+    SDM_HIP(hipMemcpyAsync(&info[0], P.info, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    SDM_HIP(hipMemcpyAsync(&info[1], P.start + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    SDM_HIP(hipStreamSynchronize(st));
+    if (info[0] != 0) {
+        *big = true;
+        return SDM_OK;
+    }
+    hipLaunchKernelGGL(k_plan_check, dim3(grid_for(info[1], 256, 4096)), dim3(256), 0, st, info[1],
+                       nc, group_begin, group_end, offsets, cap, P.info + 1);
+    SDM_LAUNCHED();
+    uint32_t bad = 0;
+    SDM_HIP(hipMemcpyAsync(&bad, P.info + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    SDM_HIP(hipStreamSynchronize(st));
+    if (bad) return SDM_OK;
+    *usable = true;
+    *n_groups = info[1];
     return SDM_OK;
 }
 

@@ -169,4 +169,27 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
 
 bool shape_valid(const LaunchShape& sh);
 
+// Arrays of the launch plan built on the device (inside a workspace).
+struct DevicePlanArrays {
+    uint8_t* jump = nullptr;          // cells of the greedy group a cell would open
+    uint8_t* exits = nullptr;         // chunk walk exits per entry
+    uint8_t* entries = nullptr;       // chunk walk entries
+    uint8_t* super_exits = nullptr;   // exits of runs of chunk tables, per entry
+    uint8_t* super_entries = nullptr;
+    uint32_t* start = nullptr;        // group-start flags, then their prefix (n_cells + 1)
+    uint32_t* info = nullptr;         // [0] large-cell flag, [1] plan check flag
+    uint32_t* tile_sums = nullptr;    // scan scratch
+};
+void carve_device_plan(Carver& c, uint32_t n_cells, DevicePlanArrays* p);
+
+// Greedy wavefront-tier groups of the cells [0, nc) (at most cap slots and
+// kGroupMaxCells cells each), built on the device from the slot offsets
+// (dev, nc + 1 entries) into group_begin / group_end (dev, nc entries each).
+// *usable = every cell holds at most cap slots and the groups passed their
+// check; then *n_groups is their number.  *big = some cell holds more than cap
+// slots.  Synchronises the stream (to read the group count).
+sdm_status device_plan(hipStream_t s, uint32_t nc, const uint32_t* offsets, uint32_t cap,
+                       const DevicePlanArrays& p, uint32_t* group_begin, uint32_t* group_end,
+                       uint32_t* n_groups, bool* usable, bool* big);
+
 }  // namespace sdm

@@ -450,179 +450,12 @@ __global__ void k_positions_out(uint64_t n, const uint32_t* id, const double* x,
     }
 }
 
-// ---------------------------------------------------------------------------
-// Launch plan on the device.  The host plan packs consecutive cells greedily
-// into wavefront groups (at most group_slots slots and kGroupMaxCells cells);
-// cells above group_slots go to other tiers.  Seen as a walk, each small cell c
-// that opens a group jumps to the first cell after the group, each large cell to
-// the next cell, and the group starts are the small cells on the walk from cell
-// 0.  Jumps are at most kGroupMaxCells long, so the walk is cut into chunks of
-// kPlanChunk cells: every chunk is walked from each of its first
-// kGroupMaxCells cells at once (one lane per entry, the jumps in LDS), giving
-// a 64-entry exit table per chunk.  The tables are chained in two levels:
-// each run of kPlanSuper chunks composes its tables into one, one thread
-// chains those, and each run then hands the entries down to its chunks.  The
-// real walk of every chunk then marks its group starts.
-// ---------------------------------------------------------------------------
-constexpr uint32_t kPlanChunk = 1024;
-constexpr uint32_t kPlanSuper = 64;   // chunks per run of the chaining
-constexpr uint8_t kPlanBig = 0x80;
-
-// jump[c] = cells in the greedy group that cell c would open (1..64), or
-// kPlanBig | 1 for a cell above group_slots.
-__global__ void k_plan_jump(uint32_t nc, const uint32_t* __restrict__ off, uint32_t cap,
-                            uint8_t* __restrict__ jump, unsigned int* __restrict__ big_flag)
-{
-    for (uint64_t c = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; c < nc;
-         c += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        const uint32_t n = off[c + 1] - off[c];
-        if (n > cap) {
-            jump[c] = kPlanBig | 1u;
-            atomicOr(big_flag, 1u);
-            continue;
-        }
-        uint32_t e = static_cast<uint32_t>(c) + 1u, slots = n;
-        while (e < nc && e - c < static_cast<uint32_t>(kGroupMaxCells)) {
-            const uint32_t m = off[e + 1] - off[e];
-            if (m > cap || slots + m > cap) break;
-            slots += m;
-            ++e;
-        }
-        jump[c] = static_cast<uint8_t>(e - c);
-    }
-}
-
-// exits[j * 64 + e]: where the walk entering chunk j at cell e leaves it
-// (offset into chunk j + 1).
-__global__ __launch_bounds__(kGroupMaxCells) void k_plan_chunks(uint32_t nc,
-                                                               const uint8_t* __restrict__ jump,
-                                                               uint8_t* __restrict__ exits)
-{
-    __shared__ uint8_t s_jump[kPlanChunk];
-    const uint32_t c0 = blockIdx.x * kPlanChunk;
-    const uint32_t len = nc - c0 < kPlanChunk ? nc - c0 : kPlanChunk;
-    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) s_jump[i] = jump[c0 + i] & 0x7Fu;
-    __syncthreads();
-    uint32_t p = threadIdx.x;
-    while (p < len) p += s_jump[p];
-    exits[static_cast<uint64_t>(blockIdx.x) * kGroupMaxCells + threadIdx.x] =
-        static_cast<uint8_t>(p - len);
-}
-
-// super_exits[S * 64 + e]: where the walk entering the first chunk of run S at
-// cell e leaves the run (offset into the chunk after it).
-__global__ __launch_bounds__(kGroupMaxCells) void k_plan_super(uint32_t n_chunks,
-                                                              const uint8_t* __restrict__ exits,
-                                                              uint8_t* __restrict__ super_exits)
-{
-    __shared__ uint8_t s_ex[kPlanSuper * kGroupMaxCells];
-    const uint32_t j0 = blockIdx.x * kPlanSuper;
-    const uint32_t nj = n_chunks - j0 < kPlanSuper ? n_chunks - j0 : kPlanSuper;
-    for (uint32_t i = threadIdx.x; i < nj * kGroupMaxCells; i += blockDim.x)
-        s_ex[i] = exits[static_cast<uint64_t>(j0) * kGroupMaxCells + i];
-    __syncthreads();
-    uint32_t e = threadIdx.x;
-    for (uint32_t j = 0; j < nj; ++j) e = s_ex[j * kGroupMaxCells + e];
-    super_exits[static_cast<uint64_t>(blockIdx.x) * kGroupMaxCells + threadIdx.x] =
-        static_cast<uint8_t>(e);
-}
-
-// one thread: the entry of every run (the walk starts at cell 0)
-__global__ void k_plan_stitch(uint32_t n_super, const uint8_t* __restrict__ super_exits,
-                              uint8_t* __restrict__ super_entries)
-{
-    uint32_t e = 0;
-    for (uint32_t S = 0; S < n_super; ++S) {
-        super_entries[S] = static_cast<uint8_t>(e);
-        e = super_exits[static_cast<uint64_t>(S) * kGroupMaxCells + e];
-    }
-}
-
-// the entry of every chunk of run S, from the run's entry
-__global__ __launch_bounds__(kGroupMaxCells) void k_plan_entries(
-    uint32_t n_chunks, const uint8_t* __restrict__ exits, const uint8_t* __restrict__ super_entries,
-    uint8_t* __restrict__ entries)
-{
-    __shared__ uint8_t s_ex[kPlanSuper * kGroupMaxCells];
-    const uint32_t j0 = blockIdx.x * kPlanSuper;
-    const uint32_t nj = n_chunks - j0 < kPlanSuper ? n_chunks - j0 : kPlanSuper;
-    for (uint32_t i = threadIdx.x; i < nj * kGroupMaxCells; i += blockDim.x)
-        s_ex[i] = exits[static_cast<uint64_t>(j0) * kGroupMaxCells + i];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t e = super_entries[blockIdx.x];
-        for (uint32_t j = 0; j < nj; ++j) {
-            entries[j0 + j] = static_cast<uint8_t>(e);
-            e = s_ex[j * kGroupMaxCells + e];
-        }
-    }
-}
-
-// start[c] = 1 for the group starts of chunk j (small cells on the walk), else 0;
-// the walk marks in LDS, the flags are written out by the whole workgroup.
-__global__ __launch_bounds__(256) void k_plan_mark(uint32_t nc, const uint8_t* __restrict__ jump,
-                                                   const uint8_t* __restrict__ entries,
-                                                   uint32_t* __restrict__ start)
-{
-    __shared__ uint8_t s_jump[kPlanChunk];
-    __shared__ uint8_t s_mark[kPlanChunk];
-    const uint32_t c0 = blockIdx.x * kPlanChunk;
-    const uint32_t len = nc - c0 < kPlanChunk ? nc - c0 : kPlanChunk;
-    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-        s_jump[i] = jump[c0 + i];
-        s_mark[i] = 0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t p = entries[blockIdx.x];
-        while (p < len) {
-            const uint8_t j = s_jump[p];
-            if (!(j & kPlanBig)) s_mark[p] = 1;
-            p += j & 0x7Fu;
-        }
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) start[c0 + i] = s_mark[i];
-}
-
-__global__ void k_plan_emit(uint32_t nc, const uint32_t* __restrict__ prefix,
-                            const uint8_t* __restrict__ jump, uint32_t* __restrict__ group_begin,
-                            uint32_t* __restrict__ group_end)
-{
-    for (uint64_t c = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; c < nc;
-         c += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        const uint32_t g = prefix[c];
-        if (prefix[c + 1] != g) {
-            group_begin[g] = static_cast<uint32_t>(c);
-            group_end[g] = static_cast<uint32_t>(c) + (jump[c] & 0x7Fu);
-        }
-    }
-}
-
-// The device plan must tile [0, nc) with groups of 1..kGroupMaxCells cells and at
-// most cap slots; anything else sets bit 0 of *bad and the host plan is used.
-__global__ void k_plan_check(uint32_t n_groups, uint32_t nc, const uint32_t* __restrict__ gb,
-                             const uint32_t* __restrict__ ge, const uint32_t* __restrict__ off,
-                             uint32_t cap, unsigned int* __restrict__ bad)
-{
-    for (uint64_t g = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; g < n_groups;
-         g += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        const uint32_t b = gb[g], e = ge[g];
-        bool ok = e > b && e - b <= static_cast<uint32_t>(kGroupMaxCells) && e <= nc &&
-                  off[e] - off[b] <= cap;
-        ok = ok && (g == 0 ? b == 0u : gb[g] == ge[g - 1]);
-        ok = ok && (g + 1 == n_groups ? e == nc : true);
-        if (!ok) atomicOr(bad, 1u);
-    }
-}
-
 struct TransportLayout {
     double *x, *z, *x_alt, *z_alt, *r_alt;
     uint64_t* xi_alt;
     uint32_t *id_alt, *cell, *tcnt, *mk, *mv, *mlo;
     uint32_t *off_alt, *inc_off, *in_low, *count, *tile_sums;
-    uint8_t *jump, *exits, *entries, *super_exits, *super_entries;
-    uint32_t *start, *plan_info;
+    DevicePlanArrays plan;
     size_t bytes;
 };
 
@@ -648,15 +481,7 @@ TransportLayout transport_layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t
     L.count = cv.take<uint32_t>(uint64_t(nc) + 1);
     const uint64_t longest = (n + 1) > (uint64_t(nc) + 1) ? (n + 1) : (uint64_t(nc) + 1);
     L.tile_sums = cv.take<uint32_t>((longest + kScanTile - 1) / kScanTile + 2);
-    const uint64_t chunks = (uint64_t(nc) + kPlanChunk - 1) / kPlanChunk + 1;
-    L.jump = cv.take<uint8_t>(uint64_t(nc) + 1);
-    L.exits = cv.take<uint8_t>(chunks * kGroupMaxCells);
-    L.entries = cv.take<uint8_t>(chunks);
-    const uint64_t supers = (chunks + kPlanSuper - 1) / kPlanSuper;
-    L.super_exits = cv.take<uint8_t>(supers * kGroupMaxCells);
-    L.super_entries = cv.take<uint8_t>(supers);
-    L.start = cv.take<uint32_t>(uint64_t(nc) + 1);
-    L.plan_info = cv.take<uint32_t>(64);
+    carve_device_plan(cv, nc, &L.plan);
     L.bytes = cv.used();
     return L;
 }
@@ -763,55 +588,17 @@ sdm_status refresh_plan(sdm_ctx* x)
     hipStream_t st = x->stream;
     const uint32_t cap = x->shape.group_slots;
     if (nc > 0) {
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, T.plan_info, uint64_t(4), 0u);
-        SDM_LAUNCHED();
-        hipLaunchKernelGGL(k_plan_jump, dim3(grid_for(nc, 256, 8192)), dim3(256), 0, st, nc,
-                           x->offsets, cap, T.jump, T.plan_info);
-        SDM_LAUNCHED();
-        const uint32_t chunks = (nc + kPlanChunk - 1) / kPlanChunk;
-        hipLaunchKernelGGL(k_plan_chunks, dim3(chunks), dim3(kGroupMaxCells), 0, st, nc, T.jump,
-                           T.exits);
-        SDM_LAUNCHED();
-        const uint32_t supers = (chunks + kPlanSuper - 1) / kPlanSuper;
-        hipLaunchKernelGGL(k_plan_super, dim3(supers), dim3(kGroupMaxCells), 0, st, chunks, T.exits,
-                           T.super_exits);
-        SDM_LAUNCHED();
-        hipLaunchKernelGGL(k_plan_stitch, dim3(1), dim3(1), 0, st, supers, T.super_exits,
-                           T.super_entries);
-        SDM_LAUNCHED();
-        hipLaunchKernelGGL(k_plan_entries, dim3(supers), dim3(kGroupMaxCells), 0, st, chunks,
-                           T.exits, T.super_entries, T.entries);
-        SDM_LAUNCHED();
-        hipLaunchKernelGGL(k_plan_mark, dim3(chunks), dim3(256), 0, st, nc, T.jump, T.entries,
-                           T.start);
-        SDM_LAUNCHED();
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, T.start + nc, uint64_t(1), 0u);
-        SDM_LAUNCHED();
-        SDM_TRY(scan_exclusive(st, T.start, T.start, uint64_t(nc) + 1, T.tile_sums));
-        hipLaunchKernelGGL(k_plan_emit, dim3(grid_for(nc, 256, 8192)), dim3(256), 0, st, nc, T.start,
-                           T.jump, x->group_begin, x->group_end);
-        SDM_LAUNCHED();
-        uint32_t info[2] = {0, 0};   // large-cell flag, group count
-        SDM_HIP(hipMemcpyAsync(&info[0], T.plan_info, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        SDM_HIP(hipMemcpyAsync(&info[1], T.start + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        SDM_HIP(hipStreamSynchronize(st));
-        if (info[0] == 0) {
-            hipLaunchKernelGGL(k_plan_check, dim3(grid_for(info[1], 256, 4096)), dim3(256), 0, st,
-                               info[1], nc, x->group_begin, x->group_end, x->offsets, cap,
-                               T.plan_info + 1);
-            SDM_LAUNCHED();
-            uint32_t bad = 0;
-            SDM_HIP(hipMemcpyAsync(&bad, T.plan_info + 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                   st));
-            SDM_HIP(hipStreamSynchronize(st));
-            if (!bad) {
-                Plan empty;
-                SDM_TRY(upload_grid(st, empty, &x->grid));
-                x->n_groups = info[1];
-                x->n_wave_cells = nc;
-                x->sizes_stale = true;
-                return SDM_OK;
-            }
+        uint32_t n_groups = 0;
+        bool usable = false, big = false;
+        SDM_TRY(device_plan(st, nc, x->offsets, cap, T.plan, x->group_begin, x->group_end,
+                            &n_groups, &usable, &big));
+        if (usable) {
+            Plan empty;
+            SDM_TRY(upload_grid(st, empty, &x->grid));
+            x->n_groups = n_groups;
+            x->n_wave_cells = nc;
+            x->sizes_stale = true;
+            return SDM_OK;
         }
     }
     x->sizes_stale = true;   // the host plan downloads the offsets first
@@ -911,13 +698,7 @@ extern "C" sdm_status sdm_transport_attach(sdm_ctx* x, void* workspace, size_t w
     T->in_low = L.in_low;
     T->count = L.count;
     T->tile_sums = L.tile_sums;
-    T->jump = L.jump;
-    T->exits = L.exits;
-    T->entries = L.entries;
-    T->super_exits = L.super_exits;
-    T->super_entries = L.super_entries;
-    T->start = L.start;
-    T->plan_info = L.plan_info;
+    T->plan = L.plan;
     x->transport = std::move(T);
     if (n > 0) {
         hipLaunchKernelGGL(k_cells_of, dim3(grid_for(n, 256, 8192)), dim3(256), 0, x->stream, n,

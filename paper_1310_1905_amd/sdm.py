@@ -107,6 +107,9 @@ def lib() -> ctypes.CDLL:
         "sdm_batch_remove": (ctypes.c_int, [_P, _i32, _P, _P]),
         "sdm_batch_info": (ctypes.c_int, [_P, _P, _P, _P]),
         "sdm_batch_destroy": (None, [_P]),
+        "sdm_static_scratch_bytes": (_sz, []),
+        "sdm_coalesce_sorted_static": (ctypes.c_int, [_P, _u64, _u32, _P, _P, _P, _P, _dbl,
+                                                      ctypes.c_int, _P, _u64, _u64, _P, _P]),
         "sdm_debug_philox": (ctypes.c_int, [_P, _u64, _P, _P, _P]),
         "sdm_debug_cbrt": (ctypes.c_int, [_P, _u64, _P, _P]),
         "sdm_debug_collide": (ctypes.c_int, [_P, _u64, ctypes.c_int, _P, _dbl, _P, _P, _P,
@@ -526,6 +529,27 @@ class Batch:
 
 
 # ------------------------------------------------------------ element-wise checks
+def coalesce_sorted_static(offsets: torch.Tensor, xi: torch.Tensor, r: torch.Tensor,
+                           dV: torch.Tensor, dt: float, kernel, seed: int, step: int,
+                           params: KernelParams | None = None, stream=None):
+    """sdm_coalesce_sorted_static: one step, in place, of SDs kept sorted by cell
+    (offsets uint32[n_cells + 1] as int32 or uint32 storage, xi int64 viewed as
+    uint64, r and dV float64, all on the device).  Returns (pair tests,
+    collisions) of the step."""
+    L = lib()
+    n_cells = int(dV.numel())
+    assert offsets.numel() == n_cells + 1
+    assert offsets.element_size() == 4 and xi.element_size() == 8
+    pt, co = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    st = L.sdm_coalesce_sorted_static(
+        _stream_ptr(stream), int(xi.numel()), n_cells, _dptr(offsets), _dptr(xi), _dptr(r),
+        _dptr(dV), float(dt), KERNELS.get(kernel, kernel),
+        ctypes.byref(params) if params is not None else None, int(seed), int(step),
+        ctypes.byref(pt), ctypes.byref(co))
+    _check(st, "sdm_coalesce_sorted_static")
+    return int(pt.value), int(co.value)
+
+
 def debug_philox(ctr: torch.Tensor, key: torch.Tensor) -> torch.Tensor:
     n = ctr.numel() // 4
     out = torch.empty(4 * n, dtype=torch.int32, device=ctr.device)
