@@ -194,7 +194,8 @@ def bench_large(args):
         "data": "synthetic",
         "config": {"workload": "large_domain_1024x1024_poisson128_geometric_dt0.5",
                    "n_sd": pop.n_sd, "n_cells": pop.n_cells, "parallelism": "single_gpu",
-                   "groups": plan[0], "wave_cells": plan[1], "grid_cells": plan[2],
+                   "groups": plan[0], "wave_cells": plan[1], "block_cells": plan[2],
+                   "grid_cells": plan[3],
                    "launch": cfg},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),

@@ -344,23 +344,28 @@ sdm_status sdm_diag_dry_moments(sdm_ctx *ctx, uint32_t k, double rd_min, double 
                                 const double *rho_d, double *out);
 
 /* Launch plan of a context: number of wave-tier groups (runs of consecutive
- * cells processed by one wavefront), cells in them, and cells of the grid tier
- * (cells with more storage slots than a group holds, each spread over many
- * workgroups).  host outputs, nullable. */
+ * cells processed by one wavefront), cells in them, cells of the workgroup
+ * tier (more storage slots than a group holds, up to block_slots: one
+ * workgroup each, the sort in LDS) and cells of the grid tier (larger, each
+ * spread over many workgroups).  host outputs, nullable. */
 sdm_status sdm_get_plan(sdm_ctx *ctx, uint32_t *groups, uint32_t *wave_cells,
-                        uint32_t *grid_cells);
+                        uint32_t *block_cells, uint32_t *grid_cells);
 
 /* Launch-shape knobs; none of them changes any result.
  *   group_slots    : storage slots one wavefront handles per group (256 or
- *                    512); cells with more slots go to the grid tier;
+ *                    512); cells with more slots go to the other tiers;
  *   groups_per_wave: groups each wavefront takes in sequence (1..64);
  *   waves_per_block: wavefronts per workgroup of the wave tier (1, 2, 4);
- *   xcd_remap      : 1 = give each of the 8 XCDs a contiguous range of groups. */
+ *   xcd_remap      : 1 = give each of the 8 XCDs a contiguous range of groups;
+ *   block_slots    : largest cell of the workgroup tier (0, 2048 or 8192,
+ *                    default 8192; 0 sends every cell above group_slots to
+ *                    the grid tier). */
 typedef struct {
     uint32_t group_slots;
     uint32_t groups_per_wave;
     uint32_t waves_per_block;
     uint32_t xcd_remap;
+    uint32_t block_slots;
 } sdm_launch_config;
 sdm_status sdm_get_launch_config(sdm_ctx *ctx, sdm_launch_config *cfg);
 sdm_status sdm_set_launch_config(sdm_ctx *ctx, const sdm_launch_config *cfg);

@@ -174,7 +174,7 @@ static sdm_status rebuild_lists(sdm_batch* b)
     for (const HostInstance& h : b->inst) {
         if (!h.live || h.n_cells == 0) continue;
         plan_cells(plan, static_cast<uint32_t>(h.cell_begin), h.cell_sizes.data(), h.n_cells,
-                   b->shape.group_slots);
+                   b->shape.group_slots, b->shape.block_slots);
     }
     plan_finish(plan);
     const size_t ng = plan.group_begin.size();

@@ -111,7 +111,8 @@ sdm_status upload_plan(sdm_ctx* x)
         x->sizes_stale = false;
     }
     Plan plan;
-    plan_cells(plan, 0, x->sizes.data(), x->n_cells, x->shape.group_slots);
+    plan_cells(plan, 0, x->sizes.data(), x->n_cells, x->shape.group_slots,
+               x->shape.block_slots);
     plan_finish(plan);
     const size_t ng = plan.group_begin.size();
     if (ng) {
@@ -560,11 +561,12 @@ extern "C" sdm_status sdm_get_layout(sdm_ctx* x, const uint32_t** offsets,
 }
 
 extern "C" sdm_status sdm_get_plan(sdm_ctx* x, uint32_t* groups, uint32_t* wave_cells,
-                                   uint32_t* grid_cells)
+                                   uint32_t* block_cells, uint32_t* grid_cells)
 {
     SDM_TRY(check_ctx(x));
     if (groups) *groups = x->n_groups;
     if (wave_cells) *wave_cells = x->n_wave_cells;
+    if (block_cells) *block_cells = x->grid.n_block;
     if (grid_cells) *grid_cells = x->grid.n_grid;
     return SDM_OK;
 }
@@ -576,6 +578,7 @@ static LaunchShape from_cfg(const sdm_launch_config& c)
     s.groups_per_wave = c.groups_per_wave;
     s.waves_per_block = c.waves_per_block;
     s.xcd_remap = c.xcd_remap;
+    s.block_slots = c.block_slots;
     return s;
 }
 
@@ -585,11 +588,13 @@ static void to_cfg(const LaunchShape& s, sdm_launch_config* c)
     c->groups_per_wave = s.groups_per_wave;
     c->waves_per_block = s.waves_per_block;
     c->xcd_remap = s.xcd_remap;
+    c->block_slots = s.block_slots;
 }
 
 static sdm_status apply_shape(sdm_ctx* x, const LaunchShape& sh)
 {
-    const bool replan = sh.group_slots != x->shape.group_slots;
+    const bool replan =
+        sh.group_slots != x->shape.group_slots || sh.block_slots != x->shape.block_slots;
     x->shape = sh;
     return replan ? upload_plan(x) : SDM_OK;
 }
@@ -673,13 +678,25 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
                     c.xcd_remap = xr;
                     cands.push_back(c);
                 }
+    // the wavefront-tier shapes first; then the workgroup-tier limit on the best of them
+    const size_t n_wave_cands = cands.size();
     hipEvent_t e0, e1;
     SDM_HIP(hipEventCreate(&e0));
     SDM_HIP(hipEventCreate(&e1));
     float best_ms = 1e30f;
     LaunchShape best = original;
     sdm_status st = SDM_OK;
-    for (const LaunchShape& c : cands) {
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        if (ci == n_wave_cands) {
+            for (uint32_t bs : {0u, kBlockSmall, kBlockLarge}) {
+                if (bs == best.block_slots) continue;
+                LaunchShape c = best;
+                c.block_slots = bs;
+                cands.push_back(c);
+            }
+            if (ci == cands.size()) break;
+        }
+        const LaunchShape c = cands[ci];
         if ((st = apply_shape(x, c)) != SDM_OK) break;
         // one untimed step, then reps timed ones
         if ((st = sdm_coalesce_step(x, dt, kernel, seed, 0)) != SDM_OK) break;

@@ -219,6 +219,14 @@ __device__ __forceinline__ double upscale_factor(uint32_t n)
     return static_cast<double>((nn * (nn - 1u)) >> 1) / static_cast<double>(nn >> 1);
 }
 
+// The same factor for 2 <= n < 2^26, where n(n-1)/2 is exact in binary64 and
+// the quotient is the integer n - 1 (n even) or n (n odd): formed directly, it
+// equals the rounded quotient bit for bit.
+__device__ __forceinline__ double upscale_factor_small(uint32_t n)
+{
+    return static_cast<double>((n & 1u) ? n : n - 1u);
+}
+
 // eq. (P_ij) in the fixed order ((xi_max K) dt / dV) scale
 __device__ __forceinline__ double collision_probability(uint64_t xi_max, double K, double dt,
                                                         double dV, double scale)

@@ -131,7 +131,7 @@ sdm_status radix_sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, u
 
 // ------------------------------------------------------------ step plan
 void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_cells,
-                uint32_t group_slots)
+                uint32_t group_slots, uint32_t block_slots)
 {
     uint32_t g_start = 0, g_slots = 0;
     bool open = false;
@@ -144,8 +144,13 @@ void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_
                 plan.group_end.push_back(c);
                 open = false;
             }
-            plan.grid.push_back(GridCell{c, 0, 0, 0, 0, 0, 0, 0});
-            plan.grid_sizes.push_back(n);
+            if (n <= block_slots) {
+                plan.block.push_back(c);
+                plan.block_sizes.push_back(n);
+            } else {
+                plan.grid.push_back(GridCell{c, 0, 0, 0, 0, 0, 0, 0});
+                plan.grid_sizes.push_back(n);
+            }
             continue;
         }
         if (open && (g_slots + n > group_slots || c - g_start >= static_cast<uint32_t>(kGroupMaxCells))) {
@@ -169,6 +174,23 @@ void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_
 
 void plan_finish(Plan& plan)
 {
+    // workgroup tier: largest cells first
+    {
+        std::vector<uint32_t> idx(plan.block.size());
+        for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
+        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) {
+            return plan.block_sizes[x] > plan.block_sizes[y];
+        });
+        std::vector<uint32_t> cells(idx.size()), sizes(idx.size());
+        plan.block_big = 0;
+        for (uint32_t i = 0; i < idx.size(); ++i) {
+            cells[i] = plan.block[idx[i]];
+            sizes[i] = plan.block_sizes[idx[i]];
+            if (sizes[i] > kBlockSmall) ++plan.block_big;
+        }
+        plan.block.swap(cells);
+        plan.block_sizes.swap(sizes);
+    }
     // grid tier: digit bits cb = ceil(log2 N) - kGridBucketLg (at most
     // kGridMaxDigitBits) and slot chunks of 2^lgc slots, lgc = max(11, lgN - 9),
     // keep the count table 2^cb * ncol below N, so that it and its sentinel fit
@@ -199,8 +221,10 @@ bool shape_valid(const LaunchShape& c)
 {
     const bool waves_ok = c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4;
     const bool slots_ok = c.group_slots == 256 || c.group_slots == 512;
-    return waves_ok && slots_ok && c.groups_per_wave >= 1 && c.groups_per_wave <= 64 &&
-           c.xcd_remap <= 1;
+    const bool block_ok = c.block_slots == 0 || c.block_slots == kBlockSmall ||
+                          c.block_slots == kBlockLarge;
+    return waves_ok && slots_ok && block_ok && c.groups_per_wave >= 1 &&
+           c.groups_per_wave <= 64 && c.xcd_remap <= 1;
 }
 
 void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g)
@@ -218,13 +242,14 @@ void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g)
     g->gbucket = c.take<uint2>(g->cap_buckets);
     g->gpchunk = c.take<uint2>(g->cap_pchunks);
     g->gtilesum = c.take<uint32_t>(g->cap_tiles);
+    g->blist = c.take<uint32_t>(g->cap_cells);
 }
 
 sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
 {
     if (plan.grid.size() > g->cap_cells || plan.gchunk.size() > g->cap_chunks ||
         plan.gtile.size() > g->cap_tiles || plan.gbucket.size() > g->cap_buckets ||
-        plan.gpchunk.size() > g->cap_pchunks) {
+        plan.gpchunk.size() > g->cap_pchunks || plan.block.size() > g->cap_cells) {
         set_error("grid-tier tables exceed their capacity");
         return SDM_ENOMEM;
     }
@@ -240,6 +265,11 @@ sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
         SDM_HIP(hipMemcpyAsync(g->gpchunk, plan.gpchunk.data(), plan.gpchunk.size() * sizeof(uint2),
                                hipMemcpyHostToDevice, s));
     }
+    if (!plan.block.empty())
+        SDM_HIP(hipMemcpyAsync(g->blist, plan.block.data(), plan.block.size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, s));
+    g->n_block = static_cast<uint32_t>(plan.block.size());
+    g->n_block_big = plan.block_big;
     g->n_grid = static_cast<uint32_t>(plan.grid.size());
     g->n_gchunk = static_cast<uint32_t>(plan.gchunk.size());
     g->n_gtile = static_cast<uint32_t>(plan.gtile.size());
@@ -261,6 +291,28 @@ void grid_args(const GridArrays& g, StepArgs* a)
     a->gpchunk = g.gpchunk;
     a->n_gpchunk = g.n_gpchunk;
     a->gtilesum = g.gtilesum;
+    a->blist = g.blist;
+    a->n_block = g.n_block;
+    a->n_block_big = g.n_block_big;
+}
+
+// Workgroup tier: 1024-thread workgroups for the cells above kBlockSmall slots
+// (the head of the list), 256-thread ones for the rest.
+template <bool BATCHED, bool PERM, bool PROBE>
+static sdm_status launch_block(hipStream_t s, const StepArgs& a)
+{
+    if (a.n_block_big > 0) {
+        hipLaunchKernelGGL((k_block_cells<kBlockLarge, 1024, BATCHED, PERM, PROBE>),
+                           dim3(a.n_block_big), dim3(1024), 0, s, a, a.blist);
+        SDM_LAUNCHED();
+    }
+    if (a.n_block > a.n_block_big) {
+        hipLaunchKernelGGL((k_block_cells<kBlockSmall, 256, BATCHED, PERM, PROBE>),
+                           dim3(a.n_block - a.n_block_big), dim3(256), 0, s, a,
+                           a.blist + a.n_block_big);
+        SDM_LAUNCHED();
+    }
+    return SDM_OK;
 }
 
 template <bool BATCHED, bool PERM, bool PROBE>
@@ -359,6 +411,7 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
             a.xcd_remap = shape.xcd_remap;
             SDM_TRY(launch_wave_probe(s, a, n_groups, shape));
         }
+        if (base.n_block > 0) SDM_TRY((launch_block<false, false, true>(s, base)));
         if (base.n_grid > 0) SDM_TRY((launch_grid<false, false, true>(s, base)));
         return SDM_OK;
     }
@@ -373,6 +426,12 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
                                   : launch_wave_any<true, false>(s, a, n_groups, shape));
         else SDM_TRY(perm ? launch_wave_any<false, true>(s, a, n_groups, shape)
                           : launch_wave_any<false, false>(s, a, n_groups, shape));
+    }
+    if (base.n_block > 0) {
+        if (batched)
+            SDM_TRY(perm ? (launch_block<true, true, false>(s, base)) : (launch_block<true, false, false>(s, base)));
+        else
+            SDM_TRY(perm ? (launch_block<false, true, false>(s, base)) : (launch_block<false, false, false>(s, base)));
     }
     if (base.n_grid > 0) {
         if (batched)

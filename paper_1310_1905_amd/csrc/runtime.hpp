@@ -122,6 +122,7 @@ struct LaunchShape {
     uint32_t groups_per_wave = 2;
     uint32_t waves_per_block = 1;
     uint32_t xcd_remap = 0;
+    uint32_t block_slots = kBlockLarge;   // largest cell of the workgroup tier (0: none)
 };
 
 // Work lists of one step: wave-tier groups of consecutive cells and the
@@ -132,6 +133,9 @@ struct Plan {
     // grid tier
     std::vector<GridCell> grid;
     std::vector<uint32_t> grid_sizes;
+    // workgroup tier: cells and their slot counts (ordered by plan_finish)
+    std::vector<uint32_t> block, block_sizes;
+    uint32_t block_big = 0;
     std::vector<uint2> gchunk, gtile, gbucket, gpchunk;
 };
 
@@ -143,20 +147,24 @@ struct GridArrays {
     uint2* gbucket = nullptr;
     uint2* gpchunk = nullptr;
     uint32_t* gtilesum = nullptr;
+    uint32_t* blist = nullptr;      // workgroup-tier cells
     uint64_t cap_cells = 0, cap_chunks = 0, cap_tiles = 0, cap_buckets = 0, cap_pchunks = 0;
     uint32_t n_grid = 0, n_gchunk = 0, n_gtile = 0, n_gbucket = 0, n_gpchunk = 0;
+    uint32_t n_block = 0, n_block_big = 0;
 };
 void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g);
 sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g);
 void grid_args(const GridArrays& g, StepArgs* a);
 
 // Append to `plan` the cells [c_begin, c_begin + n_cells) whose storage-slot
-// counts are sizes[0..): cells above group_slots go to the grid tier, the rest
-// are packed greedily into groups of at most group_slots slots and
-// kGroupMaxCells cells.
+// counts are sizes[0..): cells above block_slots go to the grid tier, cells
+// above group_slots (and up to block_slots) to the workgroup tier, the rest are
+// packed greedily into groups of at most group_slots slots and kGroupMaxCells
+// cells.
 void plan_cells(Plan& plan, uint32_t c_begin, const uint32_t* sizes, uint32_t n_cells,
-                uint32_t group_slots);
-// Per-cell parameters and work lists of the grid tier.
+                uint32_t group_slots, uint32_t block_slots);
+// Per-cell parameters and work lists of the grid tier; the workgroup-tier cells
+// in descending order of slots (ties by cell index).
 void plan_finish(Plan& plan);
 
 // Enqueue the wave-tier and grid-tier kernels for one step (base carries the

@@ -98,6 +98,11 @@ struct StepArgs {
     uint32_t n_gbucket;
     const uint2* gpchunk;         // (grid cell, first pair) per pair chunk
     uint32_t n_gpchunk;
+    // workgroup tier: cells in descending order of storage slots; the first
+    // n_block_big hold more than kBlockSmall slots
+    const uint32_t* blist;
+    uint32_t n_block;
+    uint32_t n_block_big;
     uint32_t* gtilesum;
 };
 
@@ -374,24 +379,50 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum_dpp(uint32_t v)
     return static_cast<uint32_t>(x);
 }
 
+// Where a group's slots are: its cells [c0, c1), the first slot of cell
+// c0 + lane (lanes < c1 - c0) and one past the group's last slot.
+struct GroupHead {
+    uint32_t c0, c1, o, end;
+};
+
+// A read of a table the step kernels never write, through the constant
+// address space: with a wave-uniform index it becomes a scalar load.
+__device__ __forceinline__ uint32_t load_const_u32(const uint32_t* p, uint64_t i)
+{
+    typedef const __attribute__((address_space(4))) uint32_t const_u32;
+    return ((const_u32*)p)[i];
+}
+
+__device__ __forceinline__ void fetch_head(const StepArgs& a, uint64_t gi, uint32_t lane,
+                                           GroupHead& H)
+{
+    H.c0 = load_const_u32(a.group_begin, gi);
+    H.c1 = load_const_u32(a.group_end, gi);
+    const uint32_t ncell = H.c1 - H.c0;
+    H.o = lane < ncell ? a.off_begin[H.c0 + lane] : 0u;
+    H.end = load_const_u32(a.off_end, H.c1 - 1);
+}
+
 // The slots of one group in registers, and where they came from.
 template <int K>
 struct GroupRegs {
     uint32_t c0, c1, g_first, G, o;   // o: first slot of cell c0 + lane (lanes < ncell)
+    double dv;                        // volume of cell c0 + lane (lanes < ncell)
     uint64_t xv[K];
     double rv[K];
 };
 
 template <int K, bool PERM>
-__device__ __forceinline__ void fetch_group(const StepArgs& a, uint64_t gi, uint32_t lane,
+__device__ __forceinline__ void fetch_group(const StepArgs& a, const GroupHead& H, uint32_t lane,
                                             GroupRegs<K>& R)
 {
-    R.c0 = a.group_begin[gi];
-    R.c1 = a.group_end[gi];
+    R.c0 = H.c0;
+    R.c1 = H.c1;
+    R.o = H.o;
     const uint32_t ncell = R.c1 - R.c0;
-    R.o = lane < ncell ? a.off_begin[R.c0 + lane] : 0u;
     R.g_first = readlane_u32(R.o, 0);
-    R.G = a.off_end[R.c1 - 1] - R.g_first;
+    R.G = H.end - R.g_first;
+    R.dv = lane < ncell ? a.dV[R.c0 + lane] : 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const uint32_t s = lane + k * kWave;
@@ -415,7 +446,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
     static_assert(sizeof(CollEntry) * kQueueCap >= 8u * kGroupMaxCells, "probe maxima in the queue");
     __shared__ Lds lds_all[WAVES];
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
     Lds& L = lds_all[wv];
     // probe mode: per-cell maxima (bit patterns of non-negative doubles) in the
     // otherwise unused collision queue
@@ -430,8 +461,15 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
 
     uint32_t q_head = 0, q_count = 0;
     unsigned long long pair_acc = 0, coll_acc = 0;
+    // software pipeline: the slot offsets of group g + 2 and the slots of
+    // group g + 1 are loaded while group g is processed
     GroupRegs<K> R;
-    if (g < g_end) fetch_group<K, PERM>(a, g, lane, R);
+    GroupHead Hn;
+    if (g < g_end) {
+        fetch_head(a, g, lane, Hn);
+        fetch_group<K, PERM>(a, Hn, lane, R);
+        if (g + 1 < g_end) fetch_head(a, g + 1, lane, Hn);
+    }
 
     for (; g < g_end; ++g) {
         const uint32_t c0 = R.c0;
@@ -486,8 +524,8 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
         if (has_cell) {
             L.ucb[lane] = u_incl - ucalls_l;
             L.eqn[lane] = before | (q_base << 10) | (nl << 20);
-            L.dV[lane] = a.dV[c0 + lane];
-            L.scale[lane] = nl >= 2 ? upscale_factor(nl) : 0.0;
+            L.dV[lane] = R.dv;
+            L.scale[lane] = nl >= 2 ? upscale_factor_small(nl) : 0.0;
             if constexpr (PERM) a.nlive_out[c0 + lane] = nl;
             if constexpr (PROBE) pmax[lane] = 0ull;
         }
@@ -496,7 +534,10 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
                 if (has_cell) a.cell_max[c0 + lane] = 0.0;
             }
             wave_sync();
-            if (g + 1 < g_end) fetch_group<K, PERM>(a, g + 1, lane, R);
+            if (g + 1 < g_end) {
+                fetch_group<K, PERM>(a, Hn, lane, R);
+                if (g + 2 < g_end) fetch_head(a, g + 2, lane, Hn);
+            }
             continue;
         }
         // per-slot info and per-call info, one cell at a time
@@ -635,7 +676,10 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
         }
         wave_sync();
         // the registers of this group are free: start loading the next one
-        if (g + 1 < g_end) fetch_group<K, PERM>(a, g + 1, lane, R);
+        if (g + 1 < g_end) {
+            fetch_group<K, PERM>(a, Hn, lane, R);
+            if (g + 2 < g_end) fetch_head(a, g + 2, lane, Hn);
+        }
         if constexpr (PERM) continue;
 
         // (4) uniform deviates, two pairs per Philox call
@@ -1095,6 +1139,180 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_pairs(const StepArgs a)
         if constexpr (BATCHED) atomicAdd(&a.inst[j.inst].collisions, static_cast<unsigned long long>(tot));
         else atomicAdd(a.stats + (blockIdx.x % kStatSlots) * kStatStride + 1, static_cast<unsigned long long>(tot));
     }
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup tier: one workgroup per cell of up to CAPB storage slots (more than
+// a wavefront group takes), the whole order by (key, slot) in LDS, then the
+// pair tests, in one launch over all such cells.  The sort is the wavefront
+// tier's: one most-significant-digit pass over 2^floor(log2 n) buckets with
+// LDS atomics, an exclusive scan, a scatter by (bucket start + arrival) and a
+// rank inside each bucket by full (key, slot) comparison.  The cells come
+// largest first, so that the long ones start early (longest-processing-time
+// order); each workgroup reads its cell's xi once, coalesced, and gathers
+// xi and r of the pair members from L2.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kBlockSmall = 2048;   // cells up to here take 256-thread workgroups
+constexpr uint32_t kBlockLarge = 8192;   // and up to here 1024-thread ones
+
+template <int CAPB, int T>
+struct BlockLds {
+    uint64_t kv[CAPB];          // (key << 32 | slot) grouped by bucket
+    uint32_t start[CAPB + 1];   // bucket counts, then bucket starts; start[nb] = n
+    uint32_t keys[CAPB];        // shuffle key of every slot, then the sorted order (slots)
+    uint32_t red[T / kWave];
+    double dmax[T / kWave];
+};
+
+template <int CAPB, int T, bool BATCHED, bool PERM, bool PROBE = false>
+__global__ __launch_bounds__(T) void k_block_cells(const StepArgs a, const uint32_t* list)
+{
+    constexpr int K = CAPB / T;   // storage slots per thread
+    constexpr int W = T / kWave;
+    static_assert(CAPB % T == 0 && T % kWave == 0, "block shape");
+    static_assert(!PROBE || (!BATCHED && !PERM), "probe of a single run");
+    __shared__ BlockLds<CAPB, T> L;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const uint32_t c = load_const_u32(list, blockIdx.x);
+    const CellJob j = resolve_cell<BATCHED>(a, c);
+    const uint32_t M = j.n_slots;   // <= CAPB
+
+    // (1) live SDs (coalesced), the shuffle keys of all slots (four per Philox call)
+    uint64_t xv[K];
+    uint32_t live_cnt = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t s = tid + static_cast<uint32_t>(k) * T;
+        xv[k] = s < M ? a.xi[j.off + s] : 0u;
+        live_cnt += xv[k] != 0u ? 1u : 0u;
+    }
+    for (uint32_t q = tid; 4 * q < M; q += T) {
+        const Words4 w = philox4x32_10(q, j.rng_cell, j.step, kTagShuffle, j.k0, j.k1);
+#pragma unroll
+        for (uint32_t t = 0; t < 4; ++t)
+            if (4 * q + t < M) L.keys[4 * q + t] = w.w[t];
+    }
+    const uint32_t n = block_sum<T>(live_cnt, L.red);   // also orders the key writes
+    if (n == 0) {
+        if (tid == 0) {
+            if constexpr (PERM) a.nlive_out[c] = 0;
+            if constexpr (PROBE) a.cell_max[c] = 0.0;
+        }
+        return;
+    }
+    const uint32_t lg = 31u - static_cast<uint32_t>(__clz(static_cast<int>(n)));
+    const uint32_t nb = 1u << lg;
+    for (uint32_t i = tid; i <= nb; i += T) L.start[i] = 0;
+    __syncthreads();
+
+    // (2) bucket counts on the top lg key bits
+    uint32_t key[K], bkt[K], arr[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        key[k] = 0;
+        bkt[k] = 0;
+        arr[k] = 0;
+        if (xv[k] != 0u) {
+            const uint32_t s = tid + static_cast<uint32_t>(k) * T;
+            key[k] = L.keys[s];
+            bkt[k] = bucket_of(key[k], lg);
+            arr[k] = atomicAdd(&L.start[bkt[k]], 1u);
+        }
+    }
+    __syncthreads();
+
+    // (3) exclusive scan of the nb counts (thread t owns a run of `per`); start[nb] = n
+    {
+        const uint32_t per = (nb + T - 1) / T;
+        const uint32_t b0 = tid * per;
+        const uint32_t b1 = b0 + per < nb ? b0 + per : nb;
+        uint32_t run = 0;
+        for (uint32_t b = b0; b < b1; ++b) run += L.start[b];
+        const uint32_t incl = wave_inclusive_sum_dpp(run);
+        if (lane == kWave - 1) L.red[wv] = incl;
+        __syncthreads();
+        uint32_t before = incl - run;
+#pragma unroll
+        for (int w = 0; w < W; ++w) before += static_cast<uint32_t>(w) < wv ? L.red[w] : 0u;
+        for (uint32_t b = b0; b < b1; ++b) {
+            const uint32_t cnt = L.start[b];
+            L.start[b] = before;
+            before += cnt;
+        }
+        if (tid == 0) L.start[nb] = n;
+    }
+    __syncthreads();
+
+    // (4) scatter (key, slot) to bucket start + arrival
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (xv[k] != 0u)
+            L.kv[L.start[bkt[k]] + arr[k]] =
+                (static_cast<uint64_t>(key[k]) << 32) | (tid + static_cast<uint32_t>(k) * T);
+    __syncthreads();
+
+    // (5) rank inside the bucket; the sorted order (slot at each position) replaces the keys
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (xv[k] != 0u) {
+            const uint32_t s = tid + static_cast<uint32_t>(k) * T;
+            const uint32_t lo = L.start[bkt[k]];
+            const uint32_t hi = L.start[bkt[k] + 1];
+            const uint64_t me = (static_cast<uint64_t>(key[k]) << 32) | s;
+            uint32_t rank = 0;
+            for (uint32_t e = lo; e < hi; ++e) rank += (L.kv[e] < me) ? 1u : 0u;
+            L.keys[lo + rank] = s;
+        }
+    }
+    __syncthreads();
+
+    if constexpr (PERM) {
+        for (uint32_t i = tid; i < n; i += T) a.perm_out[j.off + i] = L.keys[i];
+        if (tid == 0) a.nlive_out[c] = n;
+        return;
+    }
+    const uint32_t npairs = n >> 1;
+    const double scale = npairs ? upscale_factor_small(n) : 0.0;
+    if constexpr (PROBE) {
+        double best = 0.0;
+        for (uint32_t m = tid; m < npairs; m += T) {
+            const uint32_t sa = L.keys[2 * m], sb = L.keys[2 * m + 1];
+            const uint64_t xa = a.xi[j.off + sa], xb = a.xi[j.off + sb];
+            const double Kab = collection_kernel(j.kernel, j.kp, a.r[j.off + sa], a.r[j.off + sb]);
+            best = fmax(best, collision_probability(xa >= xb ? xa : xb, Kab, j.dt, j.dV, scale));
+        }
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) best = fmax(best, __shfl_xor(best, d, kWave));
+        if (lane == 0) L.dmax[wv] = best;
+        __syncthreads();
+        if (tid == 0) {
+            double b = L.dmax[0];
+            for (int w = 1; w < W; ++w) b = fmax(b, L.dmax[w]);
+            a.cell_max[c] = b;
+        }
+        return;
+    }
+
+    // (6) pair tests: each thread takes the two pairs of one uniform call
+    uint32_t coll = 0;
+    const uint32_t h_end = (npairs + 1u) >> 1;
+    for (uint32_t h = tid; h < h_end; h += T) {
+        const Words4 w = philox4x32_10(h, j.rng_cell, j.step, kTagUniform, j.k0, j.k1);
+#pragma unroll
+        for (uint32_t t = 0; t < 2; ++t) {
+            const uint32_t m = 2 * h + t;
+            if (m >= npairs) break;
+            const double u = t ? uniform_open01(w.w[2], w.w[3]) : uniform_open01(w.w[0], w.w[1]);
+            const uint32_t sa = L.keys[2 * m], sb = L.keys[2 * m + 1];
+            const uint64_t xa = a.xi[j.off + sa], xb = a.xi[j.off + sb];
+            const double ra = a.r[j.off + sa], rb = a.r[j.off + sb];
+            if (collide_pair_global(a, j, scale, u, sa, sb, xa, xb, ra, rb)) ++coll;
+        }
+    }
+    const uint32_t tot = block_sum<T>(coll, L.red);
+    if (tid == 0) add_counts(a, BATCHED, j.inst, blockIdx.x, npairs, tot);
 }
 
 }  // namespace sdm

@@ -34,7 +34,7 @@ class KernelParams(ctypes.Structure):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("group_slots", _u32), ("groups_per_wave", _u32), ("waves_per_block", _u32),
-                ("xcd_remap", _u32)]
+                ("xcd_remap", _u32), ("block_slots", _u32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -75,7 +75,7 @@ def lib() -> ctypes.CDLL:
         "sdm_get_stats": (ctypes.c_int, [_P, _P, _P]),
         "sdm_get_layout": (ctypes.c_int, [_P, _P, _P]),
         "sdm_debug_permutation": (ctypes.c_int, [_P, _u64, _u64, _P, _P]),
-        "sdm_get_plan": (ctypes.c_int, [_P, _P, _P, _P]),
+        "sdm_get_plan": (ctypes.c_int, [_P, _P, _P, _P, _P]),
         "sdm_set_rules": (ctypes.c_int, [_P, _u32]),
         "sdm_get_rules": (ctypes.c_int, [_P, _P]),
         "sdm_recycle": (ctypes.c_int, [_P]),
@@ -373,11 +373,11 @@ class Context:
         return order[: self.n_sd], nlive[: self.n_cells]
 
     def plan(self):
-        """(wave-tier groups, cells in them, grid-tier cells)."""
-        g, w, b = _u32(), _u32(), _u32()
-        _check(lib().sdm_get_plan(self._ctx, ctypes.byref(g), ctypes.byref(w), ctypes.byref(b)),
-               "sdm_get_plan")
-        return int(g.value), int(w.value), int(b.value)
+        """(wave-tier groups, cells in them, workgroup-tier cells, grid-tier cells)."""
+        g, w, b, d = _u32(), _u32(), _u32(), _u32()
+        _check(lib().sdm_get_plan(self._ctx, ctypes.byref(g), ctypes.byref(w), ctypes.byref(b),
+                                  ctypes.byref(d)), "sdm_get_plan")
+        return int(g.value), int(w.value), int(b.value), int(d.value)
 
     def launch_config(self) -> LaunchConfig:
         c = LaunchConfig()

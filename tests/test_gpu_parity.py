@@ -97,8 +97,9 @@ def test_many_cells_per_group(sdm_mod, oracle_mod):
     pop = synth.tiny_cells(seed=8, n_cells=3000, max_per_cell=4, xi_max=9, dead_fraction=0.2)
     ctx, ref = _run_pair(sdm_mod, oracle_mod, pop, 8, 5.0, "golovin", dV_scale=1e-9)
     _assert_same(ctx, ref, "tiny cells")
-    groups, wave_cells, grid_cells = ctx.plan()
-    assert wave_cells == pop.n_cells and grid_cells == 0 and groups <= pop.n_cells // 64 + 60
+    groups, wave_cells, block_cells, grid_cells = ctx.plan()
+    assert wave_cells == pop.n_cells and block_cells == grid_cells == 0
+    assert groups <= pop.n_cells // 64 + 60
 
 
 @pytest.mark.parametrize("kernel", ["geometric", "golovin"])
@@ -134,8 +135,8 @@ def test_grid_tier_plan_transitions(sdm_mod, oracle_mod):
     r = np.exp(g.uniform(np.log(5e-6), np.log(2e-3), n))
     dV = np.array([1e-2, 1e-1, 1e-1, 1.0, 1.0, 1.0, 10.0, 5e2, 1e3, 1e-3])
     ctx = sdm_mod.Context(cell, xi, r, dV)
-    ctx.set_launch_config(group_slots=256)
-    assert ctx.plan()[1:] == (1, len(sizes) - 1)
+    ctx.set_launch_config(group_slots=256, block_slots=0)
+    assert ctx.plan()[1:] == (1, 0, len(sizes) - 1)
     ref = oracle_mod.SlotState(cell, xi, r, dV)
     order, nlive = ctx.permutation(seed=5, step=2)
     order, nlive = order.cpu().numpy(), nlive.cpu().numpy()
@@ -149,6 +150,47 @@ def test_grid_tier_plan_transitions(sdm_mod, oracle_mod):
         ref.step_parallel(2.0, oracle_mod.GEOMETRIC, 9, t, threads=10)
     _assert_same(ctx, ref, "grid plan transitions")
     assert ref.stats[1] > 0
+
+
+@pytest.mark.parametrize("kernel", ["geometric", "golovin"])
+def test_block_tier_cells(sdm_mod, oracle_mod, kernel):
+    """Cells of the workgroup tier (one workgroup per cell, the sort in LDS): 513 to
+    8192 storage slots, with the neighbours of its limits (512/513 against the
+    wavefront groups, 2048/2049 between its 256- and 1024-thread workgroups,
+    8192/8193 against the grid tier) and dead slots: the plan splits as stated,
+    the pairing order and three steps are bit-exact; with the tier limited to
+    2048 slots, and switched off, the results are the same."""
+    g = np.random.default_rng(4242)
+    sizes = [513, 700, 1500, 2047, 2048, 2049, 3000, 5000, 8191, 8192, 8193, 40, 600, 512]
+    cell = np.repeat(np.arange(len(sizes), dtype=np.uint32), sizes)
+    n = cell.size
+    xi = g.integers(1, 40, n).astype(np.uint64)
+    xi[g.random(n) < 0.05] = 0
+    r = np.exp(g.uniform(np.log(5e-6), np.log(2e-3), n))
+    dV = g.uniform(1e-3, 1.0, len(sizes))
+    kind = oracle_mod.GOLOVIN if kernel == "golovin" else oracle_mod.GEOMETRIC
+    states = []
+    for block_slots, plan in ((8192, (2, 11, 1)), (2048, (2, 6, 6)), (0, (2, 0, 12))):
+        ctx = sdm_mod.Context(cell, xi, r, dV)
+        ctx.set_launch_config(group_slots=512, block_slots=block_slots)
+        assert ctx.plan()[1:] == plan, block_slots
+        ref = oracle_mod.SlotState(cell, xi, r, dV)
+        order, nlive = ctx.permutation(seed=11, step=4)
+        order, nlive = order.cpu().numpy(), nlive.cpu().numpy()
+        off = ref.offsets.astype(np.int64)
+        for c in range(len(sizes)):
+            exp = oracle_mod.cell_order(ref.xi[off[c]:off[c] + sizes[c]], 11, c, 4)
+            assert nlive[c] == exp.size
+            assert np.array_equal(order[off[c]:off[c] + exp.size], exp), sizes[c]
+        for t in range(3):
+            ctx.step(2.0, kernel, 11, t)
+            ref.step_parallel(2.0, kind, 11, t, threads=8)
+        _assert_same(ctx, ref, f"block tier {kernel} limit {block_slots}")
+        assert ref.stats[1] > 0
+        states.append(ctx.state_numpy())
+    for xs, rs in states[1:]:
+        assert np.array_equal(xs, states[0][0])
+        assert np.array_equal(rs.view(np.uint64), states[0][1].view(np.uint64))
 
 
 def test_grid_tier_huge_cell(sdm_mod, oracle_mod):
@@ -165,7 +207,7 @@ def test_grid_tier_huge_cell(sdm_mod, oracle_mod):
     r = np.exp(g.uniform(np.log(5e-6), np.log(2e-3), n))
     dV = np.array([1e3, 1e-3])
     ctx = sdm_mod.Context(cell, xi, r, dV)
-    assert ctx.plan()[1:] == (0, 2)
+    assert ctx.plan()[1:] == (0, 1, 1)
     ref = oracle_mod.SlotState(cell, xi, r, dV)
     order, nlive = ctx.permutation(seed=99, step=5)
     order, nlive = order.cpu().numpy(), nlive.cpu().numpy()
@@ -233,7 +275,7 @@ def test_box_golovin(sdm_mod, oracle_mod):
     pop = synth.box_golovin(seed=synth.SEEDS[2])
     ctx, ref = _run_pair(sdm_mod, oracle_mod, pop, 400, pop.dt, pop.kernel, threads=1)
     _assert_same(ctx, ref, "box golovin 400 steps")
-    assert ctx.plan()[1:] == (0, 1)
+    assert ctx.plan()[1:] == (0, 1, 0)
 
 
 def test_large_domain_reduced_full_parity(sdm_mod, oracle_mod):

@@ -186,7 +186,7 @@ def test_device_plan_many_chunks(sdm_mod):
         ctx.set_launch_config(group_slots=512)
         ctx.set_launch_config(group_slots=256)     # host plan from the same offsets
         host = ctx.plan()
-        assert dev == host and dev[1] == nx * nz and dev[2] == 0
+        assert dev == host and dev[1] == nx * nz and dev[2] == dev[3] == 0
 
 
 def test_transport_errors(sdm_mod):
