@@ -352,8 +352,8 @@ sdm_status sdm_get_plan(sdm_ctx *ctx, uint32_t *groups, uint32_t *wave_cells,
                         uint32_t *block_cells, uint32_t *grid_cells);
 
 /* Launch-shape knobs; none of them changes any result.
- *   group_slots    : storage slots one wavefront handles per group (256 or
- *                    512); cells with more slots go to the other tiers;
+ *   group_slots    : storage slots one wavefront handles per group (64, 128,
+ *                    256 or 512); cells with more slots go to the other tiers;
  *   groups_per_wave: groups each wavefront takes in sequence (1..64);
  *   waves_per_block: wavefronts per workgroup of the wave tier (1, 2, 4);
  *   xcd_remap      : 1 = give each of the 8 XCDs a contiguous range of groups;

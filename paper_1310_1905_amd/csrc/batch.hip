@@ -133,7 +133,7 @@ BatchLayout batch_layout(void* ws, size_t bytes, uint64_t max_sd, uint32_t max_c
     L.inst = cv.take<InstanceRec>(max_inst);
     L.group_begin = cv.take<uint32_t>(max_cells);
     L.group_end = cv.take<uint32_t>(max_cells);
-    carve_grid(cv, max_sd, &L.grid);
+    carve_grid(cv, max_sd, max_cells, &L.grid);
     L.err = cv.take<unsigned int>(64);
     L.local_off = cv.take<uint32_t>(uint64_t(max_cells) + 1);
     // step scratch and admission sort scratch share one region (admission

@@ -47,7 +47,7 @@ CtxLayout layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t c)
     L.dV = cv.take<double>(c);
     L.group_begin = cv.take<uint32_t>(c);
     L.group_end = cv.take<uint32_t>(c);
-    carve_grid(cv, n, &L.grid);
+    carve_grid(cv, n, c, &L.grid);
     L.stats = cv.take<unsigned long long>(uint64_t(kStatSlots) * kStatStride);
     L.err = cv.take<unsigned int>(64);
     L.probe_order = cv.take<uint32_t>(n);
@@ -667,7 +667,7 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
 
     const LaunchShape original = x->shape;
     std::vector<LaunchShape> cands;
-    for (uint32_t slots : {256u, 512u})
+    for (uint32_t slots : {64u, 128u, 256u, 512u})
         for (uint32_t gpw : {1u, 2u, 4u, 8u, 12u, 16u})
             for (uint32_t wpb : {1u, 2u, 4u})
                 for (uint32_t xr : {0u, 1u}) {
@@ -676,7 +676,7 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
                     c.groups_per_wave = gpw;
                     c.waves_per_block = wpb;
                     c.xcd_remap = xr;
-                    cands.push_back(c);
+                    if (shape_valid(c)) cands.push_back(c);
                 }
     // the wavefront-tier shapes first; then the workgroup-tier limit on the best of them
     const size_t n_wave_cands = cands.size();
@@ -692,7 +692,7 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
                 if (bs == best.block_slots) continue;
                 LaunchShape c = best;
                 c.block_slots = bs;
-                cands.push_back(c);
+                if (shape_valid(c)) cands.push_back(c);
             }
             if (ci == cands.size()) break;
         }

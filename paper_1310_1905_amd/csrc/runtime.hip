@@ -220,14 +220,17 @@ void plan_finish(Plan& plan)
 bool shape_valid(const LaunchShape& c)
 {
     const bool waves_ok = c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4;
-    const bool slots_ok = c.group_slots == 256 || c.group_slots == 512;
-    const bool block_ok = c.block_slots == 0 || c.block_slots == kBlockSmall ||
-                          c.block_slots == kBlockLarge;
+    const bool slots_ok = c.group_slots == 64 || c.group_slots == 128 || c.group_slots == 256 ||
+                          c.group_slots == 512;
+    // groups under 256 slots need the workgroup tier: the grid tier's tables are
+    // sized for cells of more than 256 slots
+    const bool block_ok = (c.block_slots == 0 && c.group_slots >= 256) ||
+                          c.block_slots == kBlockSmall || c.block_slots == kBlockLarge;
     return waves_ok && slots_ok && block_ok && c.groups_per_wave >= 1 &&
            c.groups_per_wave <= 64 && c.xcd_remap <= 1;
 }
 
-void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g)
+void carve_grid(Carver& c, uint64_t n_sd, uint32_t n_cells, GridArrays* g)
 {
     // a grid cell has more slots than the smallest group (256)
     g->cap_cells = n_sd / 257 + 1;
@@ -242,14 +245,16 @@ void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g)
     g->gbucket = c.take<uint2>(g->cap_buckets);
     g->gpchunk = c.take<uint2>(g->cap_pchunks);
     g->gtilesum = c.take<uint32_t>(g->cap_tiles);
-    g->blist = c.take<uint32_t>(g->cap_cells);
+    // a workgroup-tier cell has more slots than the smallest group (64)
+    g->cap_block = std::min<uint64_t>(n_cells, n_sd / 65 + 1);
+    g->blist = c.take<uint32_t>(g->cap_block);
 }
 
 sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
 {
     if (plan.grid.size() > g->cap_cells || plan.gchunk.size() > g->cap_chunks ||
         plan.gtile.size() > g->cap_tiles || plan.gbucket.size() > g->cap_buckets ||
-        plan.gpchunk.size() > g->cap_pchunks || plan.block.size() > g->cap_cells) {
+        plan.gpchunk.size() > g->cap_pchunks || plan.block.size() > g->cap_block) {
         set_error("grid-tier tables exceed their capacity");
         return SDM_ENOMEM;
     }
@@ -373,13 +378,17 @@ static sdm_status launch_wave_any(hipStream_t s, const StepArgs& a, uint32_t n_g
     // the dry attributes exist in single runs only, and a permutation query changes nothing
     if constexpr (!BATCHED && !PERM) {
         if (a.rd3) {
+            if (sh.group_slots == 64) return launch_wave<64, false, false, true>(s, a, n_groups, sh);
+            if (sh.group_slots == 128) return launch_wave<128, false, false, true>(s, a, n_groups, sh);
             if (sh.group_slots == 256) return launch_wave<256, false, false, true>(s, a, n_groups, sh);
             if (sh.group_slots == 512) return launch_wave<512, false, false, true>(s, a, n_groups, sh);
         }
     }
+    if (sh.group_slots == 64) return launch_wave<64, BATCHED, PERM, false>(s, a, n_groups, sh);
+    if (sh.group_slots == 128) return launch_wave<128, BATCHED, PERM, false>(s, a, n_groups, sh);
     if (sh.group_slots == 256) return launch_wave<256, BATCHED, PERM, false>(s, a, n_groups, sh);
     if (sh.group_slots == 512) return launch_wave<512, BATCHED, PERM, false>(s, a, n_groups, sh);
-    set_error("group_slots must be 256 or 512");
+    set_error("group_slots must be 64, 128, 256 or 512");
     return SDM_EINVAL;
 }
 
@@ -387,9 +396,11 @@ static sdm_status launch_wave_any(hipStream_t s, const StepArgs& a, uint32_t n_g
 static sdm_status launch_wave_probe(hipStream_t s, const StepArgs& a, uint32_t n_groups,
                                     const LaunchShape& sh)
 {
+    if (sh.group_slots == 64) return launch_wave<64, false, false, false, true>(s, a, n_groups, sh);
+    if (sh.group_slots == 128) return launch_wave<128, false, false, false, true>(s, a, n_groups, sh);
     if (sh.group_slots == 256) return launch_wave<256, false, false, false, true>(s, a, n_groups, sh);
     if (sh.group_slots == 512) return launch_wave<512, false, false, false, true>(s, a, n_groups, sh);
-    set_error("group_slots must be 256 or 512");
+    set_error("group_slots must be 64, 128, 256 or 512");
     return SDM_EINVAL;
 }
 

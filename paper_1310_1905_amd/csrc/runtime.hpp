@@ -118,7 +118,7 @@ sdm_status radix_sort_by_cell(hipStream_t s, uint64_t n, const uint32_t* cell, u
 
 // Launch shape of the step kernels (none of it changes a result).
 struct LaunchShape {
-    uint32_t group_slots = 512;      // storage slots per wave-tier group (256 or 512)
+    uint32_t group_slots = 512;      // storage slots per wave-tier group (64, 128, 256 or 512)
     uint32_t groups_per_wave = 2;
     uint32_t waves_per_block = 1;
     uint32_t xcd_remap = 0;
@@ -149,10 +149,11 @@ struct GridArrays {
     uint32_t* gtilesum = nullptr;
     uint32_t* blist = nullptr;      // workgroup-tier cells
     uint64_t cap_cells = 0, cap_chunks = 0, cap_tiles = 0, cap_buckets = 0, cap_pchunks = 0;
+    uint64_t cap_block = 0;
     uint32_t n_grid = 0, n_gchunk = 0, n_gtile = 0, n_gbucket = 0, n_gpchunk = 0;
     uint32_t n_block = 0, n_block_big = 0;
 };
-void carve_grid(Carver& c, uint64_t n_sd, GridArrays* g);
+void carve_grid(Carver& c, uint64_t n_sd, uint32_t n_cells, GridArrays* g);
 sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g);
 void grid_args(const GridArrays& g, StepArgs* a);
 

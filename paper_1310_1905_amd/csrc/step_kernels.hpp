@@ -1157,9 +1157,19 @@ constexpr uint32_t kBlockLarge = 8192;   // and up to here 1024-thread ones
 
 template <int CAPB, int T>
 struct BlockLds {
-    uint64_t kv[CAPB];          // (key << 32 | slot) grouped by bucket
-    uint32_t start[CAPB + 1];   // bucket counts, then bucket starts; start[nb] = n
-    uint32_t keys[CAPB];        // shuffle key of every slot, then the sorted order (slots)
+    static_assert(CAPB <= 65536, "slots are 16-bit");
+    union {
+        struct {
+            uint64_t kv[CAPB];          // (key << 32 | slot) grouped by bucket
+            uint32_t start[CAPB + 1];   // bucket counts, then bucket starts; start[nb] = n
+            uint32_t keys[CAPB];        // shuffle key of every slot
+        } sort;
+        struct {
+            uint64_t xi[CAPB];          // live SDs in sorted order
+            double r[CAPB];
+        } pairs;
+    };
+    uint16_t slot[CAPB];                // storage slot at each sorted position
     uint32_t red[T / kWave];
     double dmax[T / kWave];
 };
@@ -1179,20 +1189,27 @@ __global__ __launch_bounds__(T) void k_block_cells(const StepArgs a, const uint3
     const CellJob j = resolve_cell<BATCHED>(a, c);
     const uint32_t M = j.n_slots;   // <= CAPB
 
-    // (1) live SDs (coalesced), the shuffle keys of all slots (four per Philox call)
+    // (1) xi and r (coalesced), the live count, and the shuffle keys of all
+    // slots (four per Philox call)
     uint64_t xv[K];
+    double rv[K];
     uint32_t live_cnt = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const uint32_t s = tid + static_cast<uint32_t>(k) * T;
-        xv[k] = s < M ? a.xi[j.off + s] : 0u;
+        xv[k] = 0u;
+        rv[k] = 0.0;
+        if (s < M) {
+            xv[k] = a.xi[j.off + s];
+            if constexpr (!PERM) rv[k] = a.r[j.off + s];
+        }
         live_cnt += xv[k] != 0u ? 1u : 0u;
     }
     for (uint32_t q = tid; 4 * q < M; q += T) {
         const Words4 w = philox4x32_10(q, j.rng_cell, j.step, kTagShuffle, j.k0, j.k1);
 #pragma unroll
         for (uint32_t t = 0; t < 4; ++t)
-            if (4 * q + t < M) L.keys[4 * q + t] = w.w[t];
+            if (4 * q + t < M) L.sort.keys[4 * q + t] = w.w[t];
     }
     const uint32_t n = block_sum<T>(live_cnt, L.red);   // also orders the key writes
     if (n == 0) {
@@ -1204,7 +1221,7 @@ __global__ __launch_bounds__(T) void k_block_cells(const StepArgs a, const uint3
     }
     const uint32_t lg = 31u - static_cast<uint32_t>(__clz(static_cast<int>(n)));
     const uint32_t nb = 1u << lg;
-    for (uint32_t i = tid; i <= nb; i += T) L.start[i] = 0;
+    for (uint32_t i = tid; i <= nb; i += T) L.sort.start[i] = 0;
     __syncthreads();
 
     // (2) bucket counts on the top lg key bits
@@ -1216,9 +1233,9 @@ __global__ __launch_bounds__(T) void k_block_cells(const StepArgs a, const uint3
         arr[k] = 0;
         if (xv[k] != 0u) {
             const uint32_t s = tid + static_cast<uint32_t>(k) * T;
-            key[k] = L.keys[s];
+            key[k] = L.sort.keys[s];
             bkt[k] = bucket_of(key[k], lg);
-            arr[k] = atomicAdd(&L.start[bkt[k]], 1u);
+            arr[k] = atomicAdd(&L.sort.start[bkt[k]], 1u);
         }
     }
     __syncthreads();
@@ -1229,7 +1246,7 @@ __global__ __launch_bounds__(T) void k_block_cells(const StepArgs a, const uint3
         const uint32_t b0 = tid * per;
         const uint32_t b1 = b0 + per < nb ? b0 + per : nb;
         uint32_t run = 0;
-        for (uint32_t b = b0; b < b1; ++b) run += L.start[b];
+        for (uint32_t b = b0; b < b1; ++b) run += L.sort.start[b];
         const uint32_t incl = wave_inclusive_sum_dpp(run);
         if (lane == kWave - 1) L.red[wv] = incl;
         __syncthreads();
@@ -1237,11 +1254,11 @@ __global__ __launch_bounds__(T) void k_block_cells(const StepArgs a, const uint3
 #pragma unroll
         for (int w = 0; w < W; ++w) before += static_cast<uint32_t>(w) < wv ? L.red[w] : 0u;
         for (uint32_t b = b0; b < b1; ++b) {
-            const uint32_t cnt = L.start[b];
-            L.start[b] = before;
+            const uint32_t cnt = L.sort.start[b];
+            L.sort.start[b] = before;
             before += cnt;
         }
-        if (tid == 0) L.start[nb] = n;
+        if (tid == 0) L.sort.start[nb] = n;
     }
     __syncthreads();
 
@@ -1249,38 +1266,52 @@ __global__ __launch_bounds__(T) void k_block_cells(const StepArgs a, const uint3
 #pragma unroll
     for (int k = 0; k < K; ++k)
         if (xv[k] != 0u)
-            L.kv[L.start[bkt[k]] + arr[k]] =
+            L.sort.kv[L.sort.start[bkt[k]] + arr[k]] =
                 (static_cast<uint64_t>(key[k]) << 32) | (tid + static_cast<uint32_t>(k) * T);
     __syncthreads();
 
-    // (5) rank inside the bucket; the sorted order (slot at each position) replaces the keys
+    // (5) rank inside the bucket: the sorted position of every live slot
+    uint32_t pos[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        pos[k] = 0;
+        if (xv[k] != 0u) {
+            const uint32_t s = tid + static_cast<uint32_t>(k) * T;
+            const uint32_t lo = L.sort.start[bkt[k]];
+            const uint32_t hi = L.sort.start[bkt[k] + 1];
+            const uint64_t me = (static_cast<uint64_t>(key[k]) << 32) | s;
+            uint32_t rank = 0;
+            for (uint32_t e = lo; e < hi; ++e) rank += (L.sort.kv[e] < me) ? 1u : 0u;
+            pos[k] = lo + rank;
+        }
+    }
+    if constexpr (PERM) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (xv[k] != 0u) a.perm_out[j.off + pos[k]] = tid + static_cast<uint32_t>(k) * T;
+        if (tid == 0) a.nlive_out[c] = n;
+        return;
+    }
+    __syncthreads();   // the sort arrays are overwritten below
+
+    // (6) the live SDs in sorted order
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (xv[k] != 0u) {
-            const uint32_t s = tid + static_cast<uint32_t>(k) * T;
-            const uint32_t lo = L.start[bkt[k]];
-            const uint32_t hi = L.start[bkt[k] + 1];
-            const uint64_t me = (static_cast<uint64_t>(key[k]) << 32) | s;
-            uint32_t rank = 0;
-            for (uint32_t e = lo; e < hi; ++e) rank += (L.kv[e] < me) ? 1u : 0u;
-            L.keys[lo + rank] = s;
+            L.pairs.xi[pos[k]] = xv[k];
+            L.pairs.r[pos[k]] = rv[k];
+            L.slot[pos[k]] = static_cast<uint16_t>(tid + static_cast<uint32_t>(k) * T);
         }
     }
     __syncthreads();
 
-    if constexpr (PERM) {
-        for (uint32_t i = tid; i < n; i += T) a.perm_out[j.off + i] = L.keys[i];
-        if (tid == 0) a.nlive_out[c] = n;
-        return;
-    }
     const uint32_t npairs = n >> 1;
     const double scale = npairs ? upscale_factor_small(n) : 0.0;
     if constexpr (PROBE) {
         double best = 0.0;
         for (uint32_t m = tid; m < npairs; m += T) {
-            const uint32_t sa = L.keys[2 * m], sb = L.keys[2 * m + 1];
-            const uint64_t xa = a.xi[j.off + sa], xb = a.xi[j.off + sb];
-            const double Kab = collection_kernel(j.kernel, j.kp, a.r[j.off + sa], a.r[j.off + sb]);
+            const uint64_t xa = L.pairs.xi[2 * m], xb = L.pairs.xi[2 * m + 1];
+            const double Kab = collection_kernel(j.kernel, j.kp, L.pairs.r[2 * m], L.pairs.r[2 * m + 1]);
             best = fmax(best, collision_probability(xa >= xb ? xa : xb, Kab, j.dt, j.dV, scale));
         }
 #pragma unroll
@@ -1295,7 +1326,8 @@ __global__ __launch_bounds__(T) void k_block_cells(const StepArgs a, const uint3
         return;
     }
 
-    // (6) pair tests: each thread takes the two pairs of one uniform call
+    // (7) pair tests: each thread takes the two pairs of one uniform call;
+    // colliding pairs are written to their storage slots at once
     uint32_t coll = 0;
     const uint32_t h_end = (npairs + 1u) >> 1;
     for (uint32_t h = tid; h < h_end; h += T) {
@@ -1305,9 +1337,9 @@ __global__ __launch_bounds__(T) void k_block_cells(const StepArgs a, const uint3
             const uint32_t m = 2 * h + t;
             if (m >= npairs) break;
             const double u = t ? uniform_open01(w.w[2], w.w[3]) : uniform_open01(w.w[0], w.w[1]);
-            const uint32_t sa = L.keys[2 * m], sb = L.keys[2 * m + 1];
-            const uint64_t xa = a.xi[j.off + sa], xb = a.xi[j.off + sb];
-            const double ra = a.r[j.off + sa], rb = a.r[j.off + sb];
+            const uint32_t sa = L.slot[2 * m], sb = L.slot[2 * m + 1];
+            const uint64_t xa = L.pairs.xi[2 * m], xb = L.pairs.xi[2 * m + 1];
+            const double ra = L.pairs.r[2 * m], rb = L.pairs.r[2 * m + 1];
             if (collide_pair_global(a, j, scale, u, sa, sb, xa, xb, ra, rb)) ++coll;
         }
     }
