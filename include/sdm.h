@@ -176,13 +176,18 @@ typedef enum {
     /* one event when u < P_ij, never more; equal multiplicities leave the
      * larger (first in pair order) particle with multiplicity 0 and its radius */
     SDM_RULE_RELEASE = 1,
-    /* recycle zero-multiplicity particles at the start of every step (see
-     * sdm_recycle) */
-    SDM_RULE_RECYCLE = 2
+    /* recycle zero-multiplicity particles at the start of every step, within
+     * each cell (see sdm_recycle) */
+    SDM_RULE_RECYCLE = 2,
+    /* recycle them at the start of every step over the whole domain (see
+     * sdm_recycle_domain); excludes SDM_RULE_RECYCLE */
+    SDM_RULE_RECYCLE_DOMAIN = 4
 } sdm_rule;
 
 /* Set / read the rule flags every later step of the context applies (steps,
- * sub-steps, adaptive sub-steps).  Errors: SDM_EINVAL (unknown flag). */
+ * sub-steps, adaptive sub-steps).  Errors: SDM_EINVAL (unknown flag, or both
+ * recycling flags), SDM_ESTATE (SDM_RULE_RECYCLE_DOMAIN on several cells
+ * without positions attached). */
 sdm_status sdm_set_rules(sdm_ctx *ctx, uint32_t rules);
 sdm_status sdm_get_rules(sdm_ctx *ctx, uint32_t *rules);
 
@@ -194,6 +199,19 @@ sdm_status sdm_get_rules(sdm_ctx *ctx, uint32_t *rules);
  * order) and keeps the rest.  Enqueued on the context stream; uses the
  * context's probe scratch. */
 sdm_status sdm_recycle(sdm_ctx *ctx);
+
+/* Recycle now, over the whole domain: the recycling procedure of Sect. 5.1.4
+ * with no restriction to a cell (Sect. 5.1.5 sends the particles that left the
+ * domain through it too).  With z dead and L live slots in the whole storage,
+ * the min(z, L) live slots ranked first by multiplicity (largest first, ties
+ * to the lower storage slot) are the donors; in ascending slot order the k-th
+ * donor with xi >= 2 gives floor(xi / 2), its radius, its dry attributes and
+ * its position to the k-th dead slot (ascending slot order) and keeps the
+ * rest.  A recycled particle placed in another cell than its slot's joins
+ * that cell: the storage is re-sorted by cell, stable in the old storage order
+ * (layout pointers change).  Synchronises.  Errors: SDM_ESTATE (several cells
+ * and no positions attached), SDM_EDEVICE. */
+sdm_status sdm_recycle_domain(sdm_ctx *ctx);
 
 /* Total number of recycled slots since sdm_init (host out).  Synchronises. */
 sdm_status sdm_get_recycled(sdm_ctx *ctx, uint64_t *total);

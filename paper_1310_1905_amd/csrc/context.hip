@@ -27,6 +27,7 @@ struct CtxLayout {
     uint32_t* probe_order;
     double* probe_cell;
     unsigned long long* probe_max;
+    uint32_t* rd_small;   // domain-wide recycling: counters and a digit histogram
     // scratch (grid-tier sort arrays during steps; sort-by-cell arrays during init)
     uint64_t* scr_kv;
     uint64_t* scr_tmp;
@@ -53,6 +54,7 @@ CtxLayout layout(void* ws, size_t ws_bytes, uint64_t n, uint32_t c)
     L.probe_order = cv.take<uint32_t>(n);
     L.probe_cell = cv.take<double>(c);
     L.probe_max = cv.take<unsigned long long>(uint64_t(kMaxSlots) * kMaxStride);
+    L.rd_small = cv.take<uint32_t>(kRecycleDomainSmall);
     // the scratch region is shared by the step scratch and the init sort
     const uintptr_t scratch_begin = cv.cur;
     L.scr_kv = cv.take<uint64_t>(n);
@@ -220,6 +222,7 @@ extern "C" sdm_status sdm_init(sdm_ctx** out, void* stream, void* workspace, siz
     x->probe_order = L.probe_order;
     x->probe_cell = L.probe_cell;
     x->probe_max = L.probe_max;
+    x->rd_small = L.rd_small;
     x->scr_kv = L.scr_kv;
     x->scr_tmp = L.scr_tmp;
     x->scr_pos = L.scr_pos;
@@ -291,6 +294,11 @@ extern "C" sdm_status sdm_coalesce_step(sdm_ctx* x, double dt, sdm_kernel kernel
     StepArgs a;
     SDM_TRY(step_args(x, dt, kernel, seed, step, &a));
     if (x->rules & kRuleRecycle) SDM_TRY(enqueue_recycle(x));
+    if (x->rules & kRuleRecycleDomain) {
+        // the re-sort moves the storage: take the arguments again
+        SDM_TRY(recycle_domain(x));
+        SDM_TRY(step_args(x, dt, kernel, seed, step, &a));
+    }
     return launch(x, a, false);
 }
 
@@ -435,8 +443,11 @@ static sdm_status run_substeps(sdm_ctx* x, double dt, uint32_t n_substeps, sdm_k
     StepArgs a;
     SDM_TRY(step_args(x, h, kernel, seed, first_step, &a));   // validates before any launch
     for (uint32_t i = 0; i < n_substeps; ++i) {
+        if (i > 0 || recycle_first) {
+            if (x->rules & kRuleRecycle) SDM_TRY(enqueue_recycle(x));
+            if (x->rules & kRuleRecycleDomain) SDM_TRY(recycle_domain(x));
+        }
         SDM_TRY(step_args(x, h, kernel, seed, first_step + i, &a));
-        if ((x->rules & kRuleRecycle) && (i > 0 || recycle_first)) SDM_TRY(enqueue_recycle(x));
         SDM_TRY(launch(x, a, false));
     }
     return SDM_OK;
@@ -467,6 +478,7 @@ extern "C" sdm_status sdm_coalesce_adaptive(sdm_ctx* x, double dt, double p_limi
     SDM_TRY(step_args(x, dt, kernel, seed, first_step, &a));   // validates before any launch
     // recycle first, so that the probed pairing is the one the first sub-step uses
     if (x->rules & kRuleRecycle) SDM_TRY(enqueue_recycle(x));
+    if (x->rules & kRuleRecycleDomain) SDM_TRY(recycle_domain(x));
     double pmax = 0.0;
     SDM_TRY(enqueue_probe(x, dt, kernel, seed, first_step, nullptr));
     SDM_TRY(read_probe_max(x, &pmax));
@@ -479,9 +491,18 @@ extern "C" sdm_status sdm_coalesce_adaptive(sdm_ctx* x, double dt, double p_limi
 extern "C" sdm_status sdm_set_rules(sdm_ctx* x, uint32_t rules)
 {
     SDM_TRY(check_ctx(x));
-    if (rules & ~static_cast<uint32_t>(SDM_RULE_RELEASE | SDM_RULE_RECYCLE)) {
+    if (rules & ~static_cast<uint32_t>(SDM_RULE_RELEASE | SDM_RULE_RECYCLE |
+                                       SDM_RULE_RECYCLE_DOMAIN)) {
         set_error("unknown rule flags 0x%x", rules);
         return SDM_EINVAL;
+    }
+    if ((rules & SDM_RULE_RECYCLE) && (rules & SDM_RULE_RECYCLE_DOMAIN)) {
+        set_error("recycling runs within cells or over the domain, not both");
+        return SDM_EINVAL;
+    }
+    if ((rules & SDM_RULE_RECYCLE_DOMAIN) && x->n_cells > 1 && !x->transport) {
+        set_error("domain-wide recycling of several cells needs positions (sdm_transport_attach)");
+        return SDM_ESTATE;
     }
     x->rules = rules;
     return SDM_OK;
@@ -665,6 +686,10 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
     SDM_HIP(hipMemcpyAsync(st_save, x->stats, uint64_t(kStatSlots) * kStatStride * 8,
                            hipMemcpyDeviceToDevice, s));
 
+    // the candidates step without domain-wide recycling: it would re-sort the
+    // storage, which the saved state does not restore
+    const uint32_t rules_saved = x->rules;
+    x->rules &= ~static_cast<uint32_t>(kRuleRecycleDomain);
     const LaunchShape original = x->shape;
     std::vector<LaunchShape> cands;
     for (uint32_t slots : {64u, 128u, 256u, 512u})
@@ -725,6 +750,7 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
     hipStreamSynchronize(s);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    x->rules = rules_saved;
     const sdm_status st2 = apply_shape(x, st == SDM_OK ? best : original);
     if (st != SDM_OK) return st;
     if (st2 != SDM_OK) return st2;

@@ -56,6 +56,7 @@ struct sdm_ctx {
     uint32_t* probe_order = nullptr;
     double* probe_cell = nullptr;       // probe: largest P_ij per cell (when the caller keeps none)
     unsigned long long* probe_max = nullptr;
+    uint32_t* rd_small = nullptr;       // domain-wide recycling: counters and a digit histogram
     uint64_t* scr_kv = nullptr;
     uint64_t* scr_tmp = nullptr;
     uint32_t* scr_pos = nullptr;
@@ -81,4 +82,7 @@ struct sdm_ctx {
 namespace sdm {
 // Rebuild the launch plan from x->sizes and upload it (synchronises).
 sdm_status ctx_replan(sdm_ctx* x);
+// Recycling over the whole domain (synchronises; re-sorts by cell when
+// positions are attached).
+sdm_status recycle_domain(sdm_ctx* x);
 }  // namespace sdm

@@ -32,7 +32,11 @@ constexpr int kStatSlots = 64;                     // spread of the global count
 constexpr int kStatStride = 16;                    // 128 bytes between counter pairs
 
 // Outcome rules of a step (bit flags, as the public rule flags).
-enum : uint32_t { kRuleRelease = 1u, kRuleRecycle = 2u };
+enum : uint32_t { kRuleRelease = 1u, kRuleRecycle = 2u, kRuleRecycleDomain = 4u };
+// Device scratch of the domain-wide recycling: 16 counter words, then a
+// 2^kRecycleDomainDigit-entry digit histogram.
+constexpr uint32_t kRecycleDomainDigit = 12;
+constexpr uint32_t kRecycleDomainSmall = 16 + (1u << kRecycleDomainDigit);
 // Index of the recycled-slot counter within each slot of the single-run counter
 // array (a free word of every counter slot; the total is their sum).
 constexpr int kRecycledStat = 2;

@@ -6,6 +6,8 @@
 #include "context.hpp"
 
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 using namespace sdm;
 
@@ -450,6 +452,181 @@ __global__ void k_positions_out(uint64_t n, const uint32_t* id, const double* x,
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Recycling over the whole domain: the recycling procedure of Sect. 5.1.4 with
+// no restriction to a cell (Sect. 5.1.5 sends the particles that leave the
+// domain through the same procedure).  With z dead and L live slots over the
+// whole storage and take = min(z, L), the donors are the `take` live slots
+// ranked first by multiplicity (largest first, ties to the lower storage
+// slot); those with xi >= 2 are split, and in ascending slot order the i-th
+// split donor gives floor(xi / 2), its radius, its dry attributes and its
+// position (location is one of the particle attributes of Sect. 5.1) to the
+// i-th dead slot.  The threshold T, the take-th largest multiplicity, comes
+// from a radix selection on xi (12 bits per pass from the top significant
+// bit); the donors are the slots above T and the rem lowest-slot ones equal to
+// T.  Exclusive scans number the donors and the dead slots in slot order.  A
+// recycled slot whose donor lies in another cell has changed cell: the
+// storage is re-sorted with the movers' re-sort of the transport step.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRdDead = 0, kRdLive = 1, kRdMax = 2, kRdDonors = 4, kRdHist = 16;
+
+__global__ void k_rd_stats(uint64_t n, const uint64_t* __restrict__ xi, uint32_t* __restrict__ small)
+{
+    uint32_t dead = 0, live = 0;
+    unsigned long long mx = 0;
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint64_t v = xi[s];
+        if (v == 0) {
+            ++dead;
+        } else {
+            ++live;
+            mx = v > mx ? v : mx;
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        dead += __shfl_xor(dead, d, 64);
+        live += __shfl_xor(live, d, 64);
+        const unsigned long long o = __shfl_xor(mx, d, 64);
+        mx = o > mx ? o : mx;
+    }
+    if ((threadIdx.x & 63u) == 0) {
+        if (dead) atomicAdd(&small[kRdDead], dead);
+        if (live) atomicAdd(&small[kRdLive], live);
+        if (mx) atomicMax(reinterpret_cast<unsigned long long*>(small + kRdMax), mx);
+    }
+}
+
+// Histogram of bits [pos_new, pos) of the live multiplicities whose bits from
+// pos up equal `prefix` (all of them when pos is 64).
+__global__ __launch_bounds__(256) void k_rd_hist(uint64_t n, const uint64_t* __restrict__ xi,
+                                                 uint32_t pos, uint32_t pos_new, uint64_t prefix,
+                                                 uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t h[1u << kRecycleDomainDigit];
+    const uint32_t nb = 1u << (pos - pos_new);
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint64_t v = xi[s];
+        if (v != 0 && (pos >= 64 || (v >> pos) == prefix))
+            atomicAdd(&h[static_cast<uint32_t>(v >> pos_new) & (nb - 1u)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+__device__ __forceinline__ bool rd_donor(uint64_t v, uint64_t T, uint32_t eq_before, uint32_t rem)
+{
+    return v >= 2u && (v > T || (v == T && eq_before < rem));
+}
+
+__global__ void k_rd_eq(uint64_t n, const uint64_t* __restrict__ xi, uint64_t T,
+                        uint32_t* __restrict__ eq)
+{
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        eq[s] = xi[s] == T ? 1u : 0u;
+}
+
+// eq: the slots equal to T before each slot (exclusive scan of k_rd_eq)
+__global__ void k_rd_flags(uint64_t n, const uint64_t* __restrict__ xi, uint64_t T, uint32_t rem,
+                           const uint32_t* __restrict__ eq, uint32_t* __restrict__ dflag,
+                           uint32_t* __restrict__ tflag)
+{
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint64_t v = xi[s];
+        dflag[s] = rd_donor(v, T, eq[s], rem) ? 1u : 0u;
+        tflag[s] = v == 0 ? 1u : 0u;
+    }
+}
+
+// the number of donors: the exclusive prefix at the last slot plus its own flag
+__global__ void k_rd_total(uint64_t n, const uint64_t* __restrict__ xi, uint64_t T, uint32_t rem,
+                           const uint32_t* __restrict__ eq, const uint32_t* __restrict__ dpos,
+                           uint32_t* __restrict__ small)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        small[kRdDonors] = dpos[n - 1] + (rd_donor(xi[n - 1], T, eq[n - 1], rem) ? 1u : 0u);
+}
+
+__global__ void k_rd_lists(uint64_t n, const uint64_t* __restrict__ xi, uint64_t T, uint32_t rem,
+                           const uint32_t* __restrict__ eq, const uint32_t* __restrict__ dpos,
+                           const uint32_t* __restrict__ tpos, uint32_t nd,
+                           uint32_t* __restrict__ dlist, uint32_t* __restrict__ tlist)
+{
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint64_t v = xi[s];
+        if (rd_donor(v, T, eq[s], rem)) dlist[dpos[s]] = static_cast<uint32_t>(s);
+        else if (v == 0 && tpos[s] < nd) tlist[tpos[s]] = static_cast<uint32_t>(s);
+    }
+}
+
+// cell of every slot from its position (the cells the storage is sorted by)
+__global__ void k_rd_cells(uint64_t n, uint32_t nx, uint32_t nz, double dx, double dz,
+                           const double* __restrict__ x, const double* __restrict__ z,
+                           uint32_t* __restrict__ cellm)
+{
+    for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < n;
+         s += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        cellm[s] = column_of(x[s], dx, nx) + nx * column_of(z[s], dz, nz);
+}
+
+// the i-th split donor to the i-th dead slot; a recycled slot in another cell
+// than its donor is marked as a mover to the donor's cell
+__global__ void k_rd_apply(uint32_t nd, const uint32_t* __restrict__ dlist,
+                           const uint32_t* __restrict__ tlist, uint64_t* __restrict__ xi,
+                           double* __restrict__ r, double* __restrict__ rd3,
+                           double* __restrict__ kappa, double* __restrict__ px,
+                           double* __restrict__ pz, uint32_t* __restrict__ cellm,
+                           unsigned long long* __restrict__ recycled)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x) {
+        const uint32_t d = dlist[i], t = tlist[i];
+        const uint64_t v = xi[d];
+        const uint64_t half = v >> 1;
+        xi[t] = half;
+        xi[d] = v - half;
+        r[t] = r[d];
+        if (rd3) {
+            rd3[t] = rd3[d];
+            kappa[t] = kappa[d];
+        }
+        if (px) {
+            px[t] = px[d];
+            pz[t] = pz[d];
+            const uint32_t cd = cellm[d];
+            cellm[t] = cd | (cd != cellm[t] ? kMovedBit : 0u);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(recycled, static_cast<unsigned long long>(nd));
+}
+
+// movers per tile (the recycled slots that changed cell)
+__global__ __launch_bounds__(kTileThreads) void k_rd_tcnt(uint64_t n, const uint32_t* __restrict__ cellm,
+                                                          uint32_t* __restrict__ tcnt)
+{
+    __shared__ uint32_t s_w[kTileK * kTileWaves];
+    const uint64_t ntiles = (n + kTileSlots - 1) / kTileSlots;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        bool moved[kTileK];
+#pragma unroll
+        for (uint32_t k = 0; k < kTileK; ++k) {
+            const uint64_t s = tile_slot(t, k);
+            moved[k] = s < n && (cellm[s] & kMovedBit) != 0;
+        }
+        uint32_t pre[kTileK], tot = 0;
+        tile_prefix(moved, pre, s_w, &tot);
+        if (threadIdx.x == 0) tcnt[t] = tot;
+    }
+}
+
 struct TransportLayout {
     double *x, *z, *x_alt, *z_alt, *r_alt;
     uint64_t* xi_alt;
@@ -763,4 +940,135 @@ extern "C" sdm_status sdm_transport_get_positions(sdm_ctx* x, double* x_out, dou
     }
     SDM_HIP(hipStreamSynchronize(x->stream));
     return SDM_OK;
+}
+
+namespace sdm {
+
+sdm_status recycle_domain(sdm_ctx* x)
+{
+    if (x->n_cells > 1 && !x->transport) {
+        set_error("domain-wide recycling of several cells needs positions (sdm_transport_attach)");
+        return SDM_ESTATE;
+    }
+    const uint64_t n = x->n_sd;
+    if (n < 2) return SDM_OK;   // a dead and a live slot are needed
+    if (n > 0xFFFFFFFFull) {
+        set_error("domain-wide recycling takes fewer than 2^32 slots");
+        return SDM_EINVAL;
+    }
+    hipStream_t st = x->stream;
+    uint32_t* small = x->rd_small;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, small, uint64_t(kRdHist), 0u);
+    SDM_LAUNCHED();
+    const dim3 grid(grid_for(n, 256, 4096)), block(256);
+    hipLaunchKernelGGL(k_rd_stats, grid, block, 0, st, n, x->xi, small);
+    SDM_LAUNCHED();
+    uint32_t head[4] = {0, 0, 0, 0};
+    SDM_HIP(hipMemcpyAsync(head, small, sizeof(head), hipMemcpyDeviceToHost, st));
+    SDM_HIP(hipStreamSynchronize(st));
+    const uint64_t dead = head[kRdDead], live = head[kRdLive];
+    uint64_t vmax = 0;
+    std::memcpy(&vmax, head + kRdMax, sizeof(vmax));
+    if (dead == 0 || live == 0) return SDM_OK;
+    const uint64_t take = dead < live ? dead : live;
+
+    // the take-th largest multiplicity T, and how many of the slots equal to T
+    // (the lowest ones) are taken
+    uint32_t pos = 64u - static_cast<uint32_t>(__builtin_clzll(vmax));
+    uint64_t prefix = 0, remaining = take;
+    std::vector<uint32_t> h(1u << kRecycleDomainDigit);
+    uint32_t* hist = small + kRdHist;
+    while (pos > 0) {
+        const uint32_t pos_new = pos > kRecycleDomainDigit ? pos - kRecycleDomainDigit : 0u;
+        const uint32_t nb = 1u << (pos - pos_new);
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nb, 256, 64)), dim3(256), 0, st, hist,
+                           uint64_t(nb), 0u);
+        SDM_LAUNCHED();
+        hipLaunchKernelGGL(k_rd_hist, dim3(grid_for(n, 256, 2048)), dim3(256), 0, st, n, x->xi, pos,
+                           pos_new, prefix, hist);
+        SDM_LAUNCHED();
+        SDM_HIP(hipMemcpyAsync(h.data(), hist, nb * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        SDM_HIP(hipStreamSynchronize(st));
+        uint32_t d = nb - 1u;
+        while (h[d] < remaining) {
+            remaining -= h[d];
+            if (d == 0) {
+                set_error("domain-wide recycling: the multiplicity histogram lost slots");
+                return SDM_EDEVICE;
+            }
+            --d;
+        }
+        prefix = (prefix << (pos - pos_new)) | d;
+        pos = pos_new;
+    }
+    const uint64_t T = prefix;
+    const uint32_t rem = static_cast<uint32_t>(remaining);
+
+    // number the donors and the dead slots in slot order (step scratch)
+    uint32_t* eq = x->scr_cnt;
+    uint32_t* dpos = reinterpret_cast<uint32_t*>(x->scr_kv);
+    uint32_t* tpos = dpos + n;
+    uint32_t* dlist = reinterpret_cast<uint32_t*>(x->scr_tmp);
+    uint32_t* tlist = dlist + n;
+    uint32_t* tiles = x->probe_order;
+    hipLaunchKernelGGL(k_rd_eq, grid, block, 0, st, n, x->xi, T, eq);
+    SDM_LAUNCHED();
+    SDM_TRY(scan_exclusive(st, eq, eq, n, tiles));
+    hipLaunchKernelGGL(k_rd_flags, grid, block, 0, st, n, x->xi, T, rem, eq, dpos, tpos);
+    SDM_LAUNCHED();
+    SDM_TRY(scan_exclusive(st, dpos, dpos, n, tiles));
+    SDM_TRY(scan_exclusive(st, tpos, tpos, n, tiles));
+    hipLaunchKernelGGL(k_rd_total, dim3(1), dim3(64), 0, st, n, x->xi, T, rem, eq, dpos, small);
+    SDM_LAUNCHED();
+    uint32_t nd = 0;
+    SDM_HIP(hipMemcpyAsync(&nd, small + kRdDonors, sizeof(nd), hipMemcpyDeviceToHost, st));
+    SDM_HIP(hipStreamSynchronize(st));
+    if (nd == 0) return SDM_OK;
+    if (nd > take) {
+        set_error("domain-wide recycling: more donors than dead slots");
+        return SDM_EDEVICE;
+    }
+    hipLaunchKernelGGL(k_rd_lists, grid, block, 0, st, n, x->xi, T, rem, eq, dpos, tpos, nd, dlist,
+                       tlist);
+    SDM_LAUNCHED();
+    TransportState* T_ = x->transport.get();
+    if (T_) {
+        hipLaunchKernelGGL(k_rd_cells, grid, block, 0, st, n, T_->nx, T_->nz, T_->dx, T_->dz, T_->x,
+                           T_->z, T_->cell);
+        SDM_LAUNCHED();
+    }
+    hipLaunchKernelGGL(k_rd_apply, dim3(grid_for(nd, 256, 4096)), block, 0, st, nd, dlist, tlist,
+                       x->xi, x->r, x->rd3, x->kappa, T_ ? T_->x : nullptr, T_ ? T_->z : nullptr,
+                       T_ ? T_->cell : nullptr, x->stats + kRecycledStat);
+    SDM_LAUNCHED();
+    if (!T_ || x->n_cells < 2) return SDM_OK;
+    // the recycled slots that joined their donor's cell move there
+    const uint64_t ntiles = (n + kTileSlots - 1) / kTileSlots;
+    hipLaunchKernelGGL(k_rd_tcnt, dim3(tile_blocks(ntiles)), dim3(kTileThreads), 0, st, n, T_->cell,
+                       T_->tcnt);
+    SDM_LAUNCHED();
+    Flow still;   // positions stay where they are
+    still.nx = T_->nx;
+    still.nz = T_->nz;
+    still.dx = T_->dx;
+    still.dz = T_->dz;
+    still.dt = 0.0;
+    still.Lx = static_cast<double>(T_->nx) * T_->dx;
+    still.Lz = static_cast<double>(T_->nz) * T_->dz;
+    still.cx = nullptr;
+    still.cz = nullptr;
+    still.sediment = 0;
+    still.kp = to_kp(x->params);
+    return resort_moved(x, still);
+}
+
+}  // namespace sdm
+
+extern "C" sdm_status sdm_recycle_domain(sdm_ctx* x)
+{
+    if (!x) {
+        set_error("context is NULL");
+        return SDM_EINVAL;
+    }
+    return recycle_domain(x);
 }

@@ -20,7 +20,8 @@ GOLOVIN = 0
 GEOMETRIC = 1
 KERNELS = {"golovin": GOLOVIN, "geometric": GEOMETRIC}
 RULE_RELEASE = 1   # one event when u < P_ij; equal multiplicities leave a zero
-RULE_RECYCLE = 2   # recycle zero-multiplicity particles at the start of each step
+RULE_RECYCLE = 2   # recycle zero-multiplicity particles at the start of each step, per cell
+RULE_RECYCLE_DOMAIN = 4   # the same over the whole domain (positions needed for several cells)
 
 _P = ctypes.c_void_p
 _u32, _u64, _i32, _dbl, _sz = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
@@ -79,6 +80,7 @@ def lib() -> ctypes.CDLL:
         "sdm_set_rules": (ctypes.c_int, [_P, _u32]),
         "sdm_get_rules": (ctypes.c_int, [_P, _P]),
         "sdm_recycle": (ctypes.c_int, [_P]),
+        "sdm_recycle_domain": (ctypes.c_int, [_P]),
         "sdm_get_recycled": (ctypes.c_int, [_P, _P]),
         "sdm_transport_workspace_bytes": (_sz, [_u64, _u32]),
         "sdm_transport_attach": (ctypes.c_int, [_P, _P, _sz, _u32, _u32, _dbl, _dbl, _P, _P]),
@@ -277,6 +279,9 @@ class Context:
 
     def recycle(self):
         _check(lib().sdm_recycle(self._ctx), "sdm_recycle")
+
+    def recycle_domain(self):
+        _check(lib().sdm_recycle_domain(self._ctx), "sdm_recycle_domain")
 
     def recycled(self) -> int:
         v = _u64()
