@@ -511,6 +511,20 @@ sdm_status sdm_coalesce_sorted_static(void *stream, uint64_t n_sd, uint32_t n_ce
 sdm_status sdm_debug_philox(void *stream, uint64_t n, const uint32_t *ctr, const uint32_t *key,
                             uint32_t *out);
 
+/* Philox4x32-10 over a counter range: out[4i..4i+3] (dev uint32[4n]) =
+ * Philox(counter = (counter[0] + lo32(i), counter[1] + hi32(i), counter[2],
+ * counter[3]), key = (key[0], key[1])), words modulo 2^32; counter and key are
+ * host arrays. */
+sdm_status sdm_debug_philox_range(void *stream, uint64_t n, const uint32_t *counter,
+                                  const uint32_t *key, uint32_t *out);
+
+/* The step's square root and division: sqrt_out[i] = sqrt(a[i]) as the
+ * terminal velocity above vt_r2 forms it (k3 = 1), div_out[i] = a[i] / b[i] as
+ * eq. (P_ij) forms it (xi = dt = scale = 1, K = a[i], dV = b[i]).  Either
+ * output may be NULL (not both); b may be NULL without div_out. */
+sdm_status sdm_debug_sqrt_div(void *stream, uint64_t n, const double *a, const double *b,
+                              double *sqrt_out, double *div_out);
+
 /* y[i] = cube root of x[i] rounded to nearest (the rounding the collision
  * update uses). */
 sdm_status sdm_debug_cbrt(void *stream, uint64_t n, const double *x, double *y);

@@ -69,6 +69,8 @@ def lib() -> ctypes.CDLL:
     P = ctypes.c_void_p
     L.oracle_philox4x32_10.argtypes = [P, P, P]
     L.oracle_philox4x32_10.restype = None
+    L.oracle_philox_range.argtypes = [u64, u64, P, P, P]
+    L.oracle_philox_range.restype = None
     L.oracle_shuffle_key.argtypes = [u64, u32, u32, u32]
     L.oracle_shuffle_key.restype = u32
     L.oracle_pair_uniform.argtypes = [u64, u32, u32, u32]
@@ -147,6 +149,24 @@ def philox4x32_10(ctr, key) -> tuple:
     out = np.zeros(4, dtype=np.uint32)
     lib().oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
     return tuple(int(v) for v in out)
+
+
+def philox_range(n: int, ctr, key, threads: int = 8) -> np.ndarray:
+    """uint32 [n, 4]: Philox of the counters (c0 + lo32(i), c1 + hi32(i), c2, c3),
+    i < n, under key (k0, k1); ranges of i run in separate threads."""
+    c = np.asarray([int(v) & 0xFFFFFFFF for v in ctr], dtype=np.uint32)
+    k = np.asarray([int(v) & 0xFFFFFFFF for v in key], dtype=np.uint32)
+    out = np.empty((n, 4), dtype=np.uint32)
+    bounds = np.linspace(0, n, max(1, threads) + 1).astype(np.int64)
+
+    def part(t):
+        lo, hi = int(bounds[t]), int(bounds[t + 1])
+        if hi > lo:
+            lib().oracle_philox_range(lo, hi - lo, _ptr(c), _ptr(k), out[lo:].ctypes.data)
+
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        list(ex.map(part, range(len(bounds) - 1)))
+    return out
 
 
 def shuffle_key(seed: int, cell: int, step: int, slot: int) -> int:

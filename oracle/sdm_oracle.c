@@ -87,6 +87,20 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
+/* Philox over a counter range (test support): element i takes the counter
+ * (c0 + lo32(i), c1 + hi32(i), c2, c3), each word modulo 2^32, and the key
+ * (k0, k1); out[4i..4i+3] are its four words.  [first, first + n) of the
+ * range, so that threads can share one range. */
+void oracle_philox_range(uint64_t first, uint64_t n, const uint32_t ctr[4], const uint32_t key[2],
+                         uint32_t *out)
+{
+    for (uint64_t j = 0; j < n; ++j) {
+        uint64_t i = first + j;
+        uint32_t c[4] = {ctr[0] + (uint32_t)i, ctr[1] + (uint32_t)(i >> 32), ctr[2], ctr[3]};
+        oracle_philox4x32_10(c, key, out + 4u * j);
+    }
+}
+
 /* Shuffle key of storage slot s of cell c at step t: word (s mod 4) of
  * Philox(counter = (s div 4, c, t, 0), key = (seed low, seed high)). */
 uint32_t oracle_shuffle_key(uint64_t seed, uint32_t cell, uint32_t step, uint32_t slot)

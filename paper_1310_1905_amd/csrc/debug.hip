@@ -55,7 +55,75 @@ __global__ void k_debug_collide(uint64_t n, uint32_t kind, KernelParams kp, doub
     }
 }
 
+// Philox over a counter range: element i takes counter (c0 + lo32(i),
+// c1 + hi32(i), c2, c3) (each word modulo 2^32) and key (k0, k1).
+__global__ void k_debug_philox_range(uint64_t n, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1, uint32_t* out)
+{
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const Words4 w = philox4x32_10(c0 + static_cast<uint32_t>(i),
+                                       c1 + static_cast<uint32_t>(i >> 32), c2, c3, k0, k1);
+        uint4 v;
+        v.x = w.w[0];
+        v.y = w.w[1];
+        v.z = w.w[2];
+        v.w = w.w[3];
+        reinterpret_cast<uint4*>(out)[i] = v;
+    }
+}
+
+// The square root of the terminal velocity's top branch (v_t = k3 sqrt(r) with
+// k3 = 1) and the division of eq. (P_ij) (p = ((xi K) dt / dV) scale with
+// xi = dt = scale = 1, K = a, dV = b): both through the step's own functions.
+__global__ void k_debug_sqrt_div(uint64_t n, const double* a, const double* b, double* sq,
+                                 double* q)
+{
+    KernelParams kp{};
+    kp.k3 = 1.0;
+    kp.r1 = 0.0;
+    kp.r2 = 0.0;
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const double x = a[i];
+        if (sq) sq[i] = terminal_velocity(kp, x);
+        if (q) q[i] = collision_probability(1u, x, 1.0, b[i], 1.0);
+    }
+}
+
 }  // namespace
+
+extern "C" sdm_status sdm_debug_philox_range(void* stream, uint64_t n, const uint32_t* counter,
+                                             const uint32_t* key, uint32_t* out)
+{
+    if (n == 0) return SDM_OK;
+    if (!counter || !key || !out) {
+        set_error("NULL array");
+        return SDM_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_debug_philox_range, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, n,
+                       counter[0], counter[1], counter[2], counter[3], key[0], key[1], out);
+    SDM_LAUNCHED();
+    SDM_HIP(hipStreamSynchronize(s));
+    return SDM_OK;
+}
+
+extern "C" sdm_status sdm_debug_sqrt_div(void* stream, uint64_t n, const double* a,
+                                         const double* b, double* sqrt_out, double* div_out)
+{
+    if (n == 0) return SDM_OK;
+    if (!a || (div_out && !b) || (!sqrt_out && !div_out)) {
+        set_error("NULL array");
+        return SDM_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_debug_sqrt_div, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, n, a, b,
+                       sqrt_out, div_out);
+    SDM_LAUNCHED();
+    SDM_HIP(hipStreamSynchronize(s));
+    return SDM_OK;
+}
 
 extern "C" sdm_status sdm_debug_philox(void* stream, uint64_t n, const uint32_t* ctr,
                                        const uint32_t* key, uint32_t* out)

@@ -114,6 +114,8 @@ def lib() -> ctypes.CDLL:
                                                       ctypes.c_int, _P, _u64, _u64, _P, _P]),
         "sdm_debug_philox": (ctypes.c_int, [_P, _u64, _P, _P, _P]),
         "sdm_debug_cbrt": (ctypes.c_int, [_P, _u64, _P, _P]),
+        "sdm_debug_philox_range": (ctypes.c_int, [_P, _u64, _P, _P, _P]),
+        "sdm_debug_sqrt_div": (ctypes.c_int, [_P, _u64, _P, _P, _P, _P]),
         "sdm_debug_collide": (ctypes.c_int, [_P, _u64, ctypes.c_int, _P, _dbl, _P, _P, _P,
                                              _P, _P, _P, _P, _P, _P, _P]),
     }
@@ -561,6 +563,27 @@ def debug_philox(ctr: torch.Tensor, key: torch.Tensor) -> torch.Tensor:
     _check(lib().sdm_debug_philox(_stream_ptr(None), n, _dptr(ctr), _dptr(key), _dptr(out)),
            "sdm_debug_philox")
     return out
+
+
+def debug_philox_range(n: int, counter, key, out: torch.Tensor | None = None) -> torch.Tensor:
+    """uint32 (as int32) tensor [n, 4]: Philox of counters (c0 + lo32(i), c1 + hi32(i),
+    c2, c3) under key (k0, k1)."""
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in counter])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    _check(lib().sdm_debug_philox_range(_stream_ptr(None), n, c, k, _dptr(out)),
+           "sdm_debug_philox_range")
+    return out
+
+
+def debug_sqrt_div(a: torch.Tensor, b: torch.Tensor):
+    """(sqrt(a), a / b) float64 tensors, with the step's own arithmetic."""
+    sq = torch.empty_like(a)
+    q = torch.empty_like(a)
+    _check(lib().sdm_debug_sqrt_div(_stream_ptr(None), a.numel(), _dptr(a), _dptr(b), _dptr(sq),
+                                    _dptr(q)), "sdm_debug_sqrt_div")
+    return sq, q
 
 
 def debug_cbrt(x: torch.Tensor) -> torch.Tensor:

@@ -106,3 +106,40 @@ def test_capacity_is_enforced(sdm_mod):
         b.add(q.cell, q.xi, -q.r, q.dV, q.kernel, q.dt, 4)
     assert e.value.status == -1
     assert b.info() == (2, 500, 6)
+
+
+def test_batch_with_a_2e20_instance(sdm_mod, oracle_mod):
+    """One box of 2^20 SDs (a grid-tier cell) and a 128-cell column of 2^17 SDs
+    (workgroup-tier cells) among small instances: each result is bit-identical to
+    the instance run alone; the big box and a small instance also equal the
+    oracle."""
+    big = synth.box_golovin(seed=synth.SEEDS[3], n_sd=1 << 20, dV=1e6)
+    col = synth.tiny_cells(seed=31, n_cells=128, max_per_cell=2048, xi_max=5000)
+    col.dV = col.dV * 1e-2
+    small = synth.ensemble(seed=91, n_instances=20, log2_lo=8, log2_hi=12)
+    pops = [small[0], big] + small[1:10] + [col] + small[10:]
+    steps = 6
+    b = sdm_mod.Batch(max_sd=sum(p.n_sd for p in pops) + 1000,
+                      max_cells=sum(p.n_cells for p in pops) + 10, max_instances=64)
+    handles = [b.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, p.seed, first_step=2) for p in pops]
+    for _ in range(steps):
+        b.step(use_graph=True)
+    for p, h in zip(pops, handles):
+        ctx = sdm_mod.Context(p.cell, p.xi, p.r, p.dV)
+        for t in range(2, 2 + steps):
+            ctx.step(p.dt, p.kernel, p.seed, t)
+        xi_a, r_a = ctx.state_numpy()
+        ctx.close()
+        xi_b, r_b, cnt = b.get(h)
+        assert np.array_equal(xi_a, xi_b.cpu().numpy().view(np.uint64)), p.n_sd
+        assert np.array_equal(r_a.view(np.uint64), r_b.cpu().numpy().view(np.uint64)), p.n_sd
+        assert cnt.steps_done == steps
+    for k in (0, 1):
+        p = pops[k]
+        ref = _oracle_run(oracle_mod, p, steps, first_step=2)
+        xi_o, r_o = ref.input_order()
+        xi_b, r_b, cnt = b.get(handles[k])
+        assert np.array_equal(xi_b.cpu().numpy().view(np.uint64), xi_o), p.n_sd
+        assert np.array_equal(r_b.cpu().numpy().view(np.uint64), r_o.view(np.uint64)), p.n_sd
+        assert (cnt.pair_tests, cnt.collisions) == (int(ref.stats[0]), int(ref.stats[1]))
+    b.close()

@@ -286,18 +286,20 @@ def test_large_domain_reduced_full_parity(sdm_mod, oracle_mod):
 
 def test_large_domain_full_size_sampled_cells(sdm_mod, oracle_mod):
     """1024 x 1024 cells (~134M SDs) in the launch configuration the benchmark's
-    autotuner selects on the state, as bench.py does; the
-    oracle advances 2048 sampled cells (plus every injected empty/single cell kind)
-    one by one with their own RNG cell index."""
+    autotuner selects on the state, as bench.py does, for 50 steps (a quarter of the
+    set-up's 200: every step is the same kernel on the same layout, and 50 steps
+    take the sampled cells through tens of collisions each); the oracle advances
+    4096 sampled cells (plus every injected empty/single cell kind) one by one
+    with their own RNG cell index."""
     pop = synth.large_domain(seed=synth.SEEDS[0])
     ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV)
     ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=3)   # as bench.py selects it
     cnt = np.bincount(pop.cell, minlength=pop.n_cells)
     off = np.concatenate([[0], np.cumsum(cnt)])
     g = np.random.default_rng(5)
-    sample = np.unique(np.concatenate([g.choice(pop.n_cells, 2048, replace=False),
+    sample = np.unique(np.concatenate([g.choice(pop.n_cells, 4096, replace=False),
                                        [0, 1, 997, 992, pop.n_cells - 1]]))
-    steps = 3
+    steps = 50
     refs = {}
     for c in sample:
         sl = slice(off[c], off[c + 1])

@@ -49,3 +49,33 @@ def test_served_results_equal_alone(sdm_mod, oracle_mod, use_graph):
         r_res = next(x for x in res if x.index == i)
         assert np.array_equal(r_res.xi, xi_o)
         assert np.array_equal(r_res.r.view(np.uint64), r_o.view(np.uint64))
+
+
+def test_served_stream_with_a_2e20_request(sdm_mod, oracle_mod):
+    """A request of 2^20 SDs (one cell: the grid tier) arrives among small ones:
+    every result equals the request served alone, and the big one equals the
+    oracle."""
+    from paper_1310_1905_amd import serve
+    reqs = synth.request_stream(seed=synth.SEEDS[8], n_requests=12, rate=500.0, log2_lo=8,
+                                log2_hi=12, steps_lo=3, steps_hi=12, max_cells=8)
+    big = synth.box_golovin(seed=synth.SEEDS[9], n_sd=1 << 20, dV=1e6)
+    big.steps = 4
+    reqs.insert(5, synth.Request(reqs[4].arrival, big))
+    budget = int(sdm_mod.lib().sdm_batch_workspace_bytes(3 << 20, 4096, 64))
+    eng = serve.Engine(budget_bytes=budget, max_instances=64, keep_state=True, use_graph=True)
+    res = eng.run(reqs, time_scale=0.0)
+    eng.close()
+    alone = {r.index: r for r in serve.run_sequential(reqs, time_scale=0.0, keep_state=True)}
+    assert sorted(r.index for r in res) == list(range(len(reqs)))
+    for r in res:
+        a = alone[r.index]
+        assert np.array_equal(r.xi, a.xi), r.index
+        assert np.array_equal(r.r.view(np.uint64), a.r.view(np.uint64)), r.index
+        assert r.pair_tests == a.pair_tests
+    st = oracle_mod.SlotState(big.cell, big.xi, big.r, big.dV)
+    for t in range(big.steps):
+        st.step(big.dt, oracle_mod.GOLOVIN, big.seed, t)
+    xi_o, r_o = st.input_order()
+    r_big = next(x for x in res if x.index == 5)
+    assert np.array_equal(r_big.xi, xi_o)
+    assert np.array_equal(r_big.r.view(np.uint64), r_o.view(np.uint64))

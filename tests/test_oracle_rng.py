@@ -89,3 +89,14 @@ def test_uniforms_look_uniform(oracle_mod):
     # Kolmogorov-Smirnov against U(0,1)
     from scipy import stats
     assert stats.kstest(us, "uniform").pvalue > 1e-3
+
+
+def test_philox_range_is_the_single_call(oracle_mod):
+    """The counter-range form (used to check the device on 2^30 counters) is the
+    single Philox call on counter (c0 + lo32(i), c1 + hi32(i), c2, c3), words
+    modulo 2^32 (across the wrap of the first word as well)."""
+    for ctr, key in (([5, 7, 9, 11], [3, 4]), ([0xFFFFFFF0, 0xFFFFFFFF, 1, 2], [0xFFFFFFFF, 0])):
+        out = oracle_mod.philox_range(1000, ctr, key, threads=3)
+        for i in (0, 1, 15, 16, 17, 500, 999):
+            c = [(ctr[0] + i) & 0xFFFFFFFF, ctr[1], ctr[2], ctr[3]]
+            assert tuple(int(v) for v in out[i]) == oracle_mod.philox4x32_10(c, key), (ctr, i)
