@@ -461,6 +461,24 @@ sdm_status sdm_batch_remove(sdm_batch *b, int32_t handle, uint64_t *xi_out, doub
 sdm_status sdm_batch_info(sdm_batch *b, uint32_t *n_instances, uint64_t *free_sd,
                           uint32_t *free_cells);
 
+/* Launch shape of a batch's steps (as sdm_set_launch_config; results do not
+ * depend on it).  Setting it re-plans the work lists and re-captures the graph
+ * at the next step.  Errors: SDM_EINVAL (NULL, out of range). */
+sdm_status sdm_batch_get_launch_config(sdm_batch *b, sdm_launch_config *cfg);
+sdm_status sdm_batch_set_launch_config(sdm_batch *b, const sdm_launch_config *cfg);
+
+/* Time every launch shape of a candidate set on the admitted instances (each
+ * candidate runs reps steps of all of them), keep the fastest, and restore every
+ * instance exactly as it was (multiplicities, radii, step counters, counters).
+ * Needs sdm_batch_autotune_workspace_bytes() bytes of device scratch
+ * (caller-owned, 256-byte aligned: 16 B per SD of capacity and one record per
+ * instance slot).  best_out (host, nullable) gets the choice.  Synchronises.
+ * Errors: SDM_EINVAL (NULL batch), SDM_ENOMEM (scratch too small or
+ * misaligned), SDM_EDEVICE. */
+size_t sdm_batch_autotune_workspace_bytes(sdm_batch *b);
+sdm_status sdm_batch_autotune(sdm_batch *b, void *scratch, size_t scratch_bytes, uint32_t reps,
+                              sdm_launch_config *best_out);
+
 void sdm_batch_destroy(sdm_batch *b);
 
 /* ------------------------------------------------------------------------ */

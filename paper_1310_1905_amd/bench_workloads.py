@@ -67,6 +67,8 @@ def run_ensemble(args):
     log(f"ensemble: {len(pops)} instances, {n_sd} SDs")
     b = sdm.Batch(n_sd, len(pops), len(pops))
     handles = [b.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, p.seed) for p in pops]
+    launch = b.autotune(reps=3).as_dict() if getattr(args, "autotune", True) else None
+    log(f"ensemble: batch launch config {b.launch_config().as_dict()}")
     for _ in range(args.warmup):
         b.step(use_graph=True)
     torch.cuda.synchronize()
@@ -106,7 +108,7 @@ def run_ensemble(args):
                      np.array_equal(ra.view(np.uint64), rb.cpu().numpy().view(np.uint64)))
         ref.close()
     return _line(args, batched, wall_b * 1e3 / args.steps, "ensemble_4096_boxes_batched_graph",
-                 {"n_sd": n_sd, "instances": len(pops),
+                 {"n_sd": n_sd, "instances": len(pops), "launch": launch,
                   "plain_launch_pair_tests_per_s": plain,
                   "plain_ms_per_step": wall_p * 1e3 / plain_steps,
                   "speedup_vs_plain": batched / plain, "bit_identical_to_plain": same})
@@ -271,7 +273,7 @@ def secondary(args):
     ens = run_ensemble(sub(steps=30, warmup=3))
     c = ens["config"]
     out["ensemble"] = {"workload": c["workload"], "instances": c["instances"], "n_sd": c["n_sd"],
-                       "ms_per_batch_step": ens["ms_per_step"],
+                       "launch": c["launch"], "ms_per_batch_step": ens["ms_per_step"],
                        "pair_tests_per_s": ens["value"],
                        "plain_ms_per_step": c["plain_ms_per_step"],
                        "plain_pair_tests_per_s": c["plain_launch_pair_tests_per_s"],

@@ -474,6 +474,145 @@ extern "C" sdm_status sdm_batch_info(sdm_batch* b, uint32_t* n_instances, uint64
     return SDM_OK;
 }
 
+extern "C" sdm_status sdm_batch_get_launch_config(sdm_batch* b, sdm_launch_config* cfg)
+{
+    if (!b || !cfg) {
+        set_error("NULL argument");
+        return SDM_EINVAL;
+    }
+    cfg->group_slots = b->shape.group_slots;
+    cfg->groups_per_wave = b->shape.groups_per_wave;
+    cfg->waves_per_block = b->shape.waves_per_block;
+    cfg->xcd_remap = b->shape.xcd_remap;
+    cfg->block_slots = b->shape.block_slots;
+    return SDM_OK;
+}
+
+static sdm_status batch_apply_shape(sdm_batch* b, const LaunchShape& sh)
+{
+    const bool replan =
+        sh.group_slots != b->shape.group_slots || sh.block_slots != b->shape.block_slots;
+    b->shape = sh;
+    b->dirty = true;   // the captured graph holds the old launches
+    return replan ? rebuild_lists(b) : SDM_OK;
+}
+
+extern "C" sdm_status sdm_batch_set_launch_config(sdm_batch* b, const sdm_launch_config* cfg)
+{
+    if (!b || !cfg) {
+        set_error("NULL argument");
+        return SDM_EINVAL;
+    }
+    LaunchShape sh;
+    sh.group_slots = cfg->group_slots;
+    sh.groups_per_wave = cfg->groups_per_wave;
+    sh.waves_per_block = cfg->waves_per_block;
+    sh.xcd_remap = cfg->xcd_remap;
+    sh.block_slots = cfg->block_slots;
+    if (!shape_valid(sh)) {
+        set_error("launch config out of range");
+        return SDM_EINVAL;
+    }
+    return batch_apply_shape(b, sh);
+}
+
+extern "C" size_t sdm_batch_autotune_workspace_bytes(sdm_batch* b)
+{
+    if (!b) return 0;
+    Carver cv;
+    cv.take<uint64_t>(b->max_sd);
+    cv.take<double>(b->max_sd);
+    cv.take<InstanceRec>(b->max_inst);
+    return cv.used();
+}
+
+extern "C" sdm_status sdm_batch_autotune(sdm_batch* b, void* scratch, size_t scratch_bytes,
+                                         uint32_t reps, sdm_launch_config* best_out)
+{
+    if (!b) {
+        set_error("batch is NULL");
+        return SDM_EINVAL;
+    }
+    if (!scratch || scratch_bytes < sdm_batch_autotune_workspace_bytes(b) ||
+        (reinterpret_cast<uintptr_t>(scratch) & 255u)) {
+        set_error("autotune scratch must be 256-byte aligned and hold %zu bytes",
+                  sdm_batch_autotune_workspace_bytes(b));
+        return SDM_ENOMEM;
+    }
+    if (reps == 0) reps = 3;
+    hipStream_t s = b->stream;
+    Carver cv(scratch, scratch_bytes);
+    uint64_t* xi_save = cv.take<uint64_t>(b->max_sd);
+    double* r_save = cv.take<double>(b->max_sd);
+    InstanceRec* inst_save = cv.take<InstanceRec>(b->max_inst);
+    SDM_HIP(hipMemcpyAsync(xi_save, b->L.xi, b->max_sd * 8, hipMemcpyDeviceToDevice, s));
+    SDM_HIP(hipMemcpyAsync(r_save, b->L.r, b->max_sd * 8, hipMemcpyDeviceToDevice, s));
+    SDM_HIP(hipMemcpyAsync(inst_save, b->L.inst, b->max_inst * sizeof(InstanceRec),
+                           hipMemcpyDeviceToDevice, s));
+    const LaunchShape original = b->shape;
+    std::vector<LaunchShape> cands;
+    for (uint32_t slots : {64u, 128u, 256u, 512u})
+        for (uint32_t gpw : {1u, 2u, 4u, 8u, 16u})
+            for (uint32_t wpb : {1u, 2u, 4u})
+                for (uint32_t xr : {0u, 1u}) {
+                    LaunchShape c = original;
+                    c.group_slots = slots;
+                    c.groups_per_wave = gpw;
+                    c.waves_per_block = wpb;
+                    c.xcd_remap = xr;
+                    if (shape_valid(c)) cands.push_back(c);
+                }
+    const size_t n_wave_cands = cands.size();
+    hipEvent_t e0, e1;
+    SDM_HIP(hipEventCreate(&e0));
+    SDM_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    LaunchShape best = original;
+    sdm_status st = SDM_OK;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        if (ci == n_wave_cands) {   // then the workgroup-tier limit on the best of them
+            for (uint32_t bs : {0u, kBlockSmall, kBlockLarge}) {
+                if (bs == best.block_slots) continue;
+                LaunchShape c = best;
+                c.block_slots = bs;
+                if (shape_valid(c)) cands.push_back(c);
+            }
+            if (ci == cands.size()) break;
+        }
+        const LaunchShape c = cands[ci];
+        if ((st = batch_apply_shape(b, c)) != SDM_OK) break;
+        if ((st = enqueue_step(b)) != SDM_OK) break;   // untimed
+        hipEventRecord(e0, s);
+        for (uint32_t i = 0; i < reps && st == SDM_OK; ++i) st = enqueue_step(b);
+        if (st != SDM_OK) break;
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+        // every instance as it was before the candidate ran
+        hipMemcpyAsync(b->L.xi, xi_save, b->max_sd * 8, hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(b->L.r, r_save, b->max_sd * 8, hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(b->L.inst, inst_save, b->max_inst * sizeof(InstanceRec),
+                       hipMemcpyDeviceToDevice, s);
+    }
+    hipMemcpyAsync(b->L.xi, xi_save, b->max_sd * 8, hipMemcpyDeviceToDevice, s);
+    hipMemcpyAsync(b->L.r, r_save, b->max_sd * 8, hipMemcpyDeviceToDevice, s);
+    hipMemcpyAsync(b->L.inst, inst_save, b->max_inst * sizeof(InstanceRec),
+                   hipMemcpyDeviceToDevice, s);
+    hipStreamSynchronize(s);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    const sdm_status st2 = batch_apply_shape(b, st == SDM_OK ? best : original);
+    if (st != SDM_OK) return st;
+    if (st2 != SDM_OK) return st2;
+    if (best_out) SDM_TRY(sdm_batch_get_launch_config(b, best_out));
+    return SDM_OK;
+}
+
 extern "C" void sdm_batch_destroy(sdm_batch* b)
 {
     if (!b) return;

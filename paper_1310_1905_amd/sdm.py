@@ -109,6 +109,10 @@ def lib() -> ctypes.CDLL:
         "sdm_batch_remove": (ctypes.c_int, [_P, _i32, _P, _P]),
         "sdm_batch_info": (ctypes.c_int, [_P, _P, _P, _P]),
         "sdm_batch_destroy": (None, [_P]),
+        "sdm_batch_get_launch_config": (ctypes.c_int, [_P, _P]),
+        "sdm_batch_set_launch_config": (ctypes.c_int, [_P, _P]),
+        "sdm_batch_autotune_workspace_bytes": (_sz, [_P]),
+        "sdm_batch_autotune": (ctypes.c_int, [_P, _P, _sz, _u32, _P]),
         "sdm_static_scratch_bytes": (_sz, []),
         "sdm_coalesce_sorted_static": (ctypes.c_int, [_P, _u64, _u32, _P, _P, _P, _P, _dbl,
                                                       ctypes.c_int, _P, _u64, _u64, _P, _P]),
@@ -516,6 +520,32 @@ class Batch:
         if with_state:
             return xi[:n], r[:n]
         return None, None
+
+    def launch_config(self) -> LaunchConfig:
+        c = LaunchConfig()
+        _check(lib().sdm_batch_get_launch_config(self._b, ctypes.byref(c)),
+               "sdm_batch_get_launch_config")
+        return c
+
+    def set_launch_config(self, **kw):
+        c = self.launch_config()
+        for k, v in kw.items():
+            setattr(c, k, int(v))
+        _check(lib().sdm_batch_set_launch_config(self._b, ctypes.byref(c)),
+               "sdm_batch_set_launch_config")
+
+    def autotune(self, reps: int = 3) -> LaunchConfig:
+        """Pick the fastest launch shape for the admitted instances (state unchanged)."""
+        L = lib()
+        nbytes = int(L.sdm_batch_autotune_workspace_bytes(self._b))
+        scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = scratch.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        best = LaunchConfig()
+        torch.cuda.synchronize(self.device)
+        _check(L.sdm_batch_autotune(self._b, aligned, nbytes + 256 - (aligned - base), int(reps),
+                                    ctypes.byref(best)), "sdm_batch_autotune")
+        return best
 
     def info(self):
         n, fsd, fc = _u32(), _u64(), _u32()

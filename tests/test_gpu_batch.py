@@ -143,3 +143,35 @@ def test_batch_with_a_2e20_instance(sdm_mod, oracle_mod):
         assert np.array_equal(r_b.cpu().numpy().view(np.uint64), r_o.view(np.uint64)), p.n_sd
         assert (cnt.pair_tests, cnt.collisions) == (int(ref.stats[0]), int(ref.stats[1]))
     b.close()
+
+
+def test_batch_autotune_keeps_every_instance(sdm_mod, oracle_mod):
+    """The batch autotuner times launch shapes on the admitted instances and
+    restores them exactly: steps after it are bit-identical to a batch that never
+    autotuned, and to the oracle."""
+    pops = _mixed_instances(12, seed=41)
+    steps = 5
+    runs = []
+    for tune in (False, True):
+        b = sdm_mod.Batch(max_sd=sum(p.n_sd for p in pops) + 100,
+                          max_cells=sum(p.n_cells for p in pops) + 10, max_instances=32)
+        hs = [b.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, p.seed, first_step=3) for p in pops]
+        b.step(use_graph=True)
+        if tune:
+            cfg = b.autotune(reps=2)
+            assert cfg.as_dict() == b.launch_config().as_dict()
+        for _ in range(steps - 1):
+            b.step(use_graph=True)
+        runs.append([b.get(h) for h in hs])
+        b.close()
+    for (xa, ra, ca), (xb, rb, cb) in zip(*runs):
+        assert np.array_equal(xa.cpu().numpy(), xb.cpu().numpy())
+        assert np.array_equal(ra.cpu().numpy().view(np.uint64), rb.cpu().numpy().view(np.uint64))
+        assert (ca.steps_done, ca.pair_tests, ca.collisions) == \
+            (cb.steps_done, cb.pair_tests, cb.collisions)
+    p = pops[-1]
+    ref = _oracle_run(oracle_mod, p, steps, first_step=3)
+    xi_o, r_o = ref.input_order()
+    xb, rb, _ = runs[1][-1]
+    assert np.array_equal(xb.cpu().numpy().view(np.uint64), xi_o)
+    assert np.array_equal(rb.cpu().numpy().view(np.uint64), r_o.view(np.uint64))
