@@ -377,13 +377,19 @@ sdm_status sdm_get_plan(sdm_ctx *ctx, uint32_t *groups, uint32_t *wave_cells,
  *   xcd_remap      : 1 = give each of the 8 XCDs a contiguous range of groups;
  *   block_slots    : largest cell of the workgroup tier (0, 2048 or 8192,
  *                    default 8192; 0 sends every cell above group_slots to
- *                    the grid tier). */
+ *                    the grid tier);
+ *   block_split    : single runs only (a batch takes 0): every workgroup-tier
+ *                    cell is spread over 2^block_split workgroups (0..5,
+ *                    default 0), each taking the SDs of one top-key-bits
+ *                    digit, for runs with too few such cells to fill the
+ *                    GPU one workgroup each; needs block_slots > 0. */
 typedef struct {
     uint32_t group_slots;
     uint32_t groups_per_wave;
     uint32_t waves_per_block;
     uint32_t xcd_remap;
     uint32_t block_slots;
+    uint32_t block_split;
 } sdm_launch_config;
 sdm_status sdm_get_launch_config(sdm_ctx *ctx, sdm_launch_config *cfg);
 sdm_status sdm_set_launch_config(sdm_ctx *ctx, const sdm_launch_config *cfg);

@@ -485,6 +485,7 @@ extern "C" sdm_status sdm_batch_get_launch_config(sdm_batch* b, sdm_launch_confi
     cfg->waves_per_block = b->shape.waves_per_block;
     cfg->xcd_remap = b->shape.xcd_remap;
     cfg->block_slots = b->shape.block_slots;
+    cfg->block_split = 0;
     return SDM_OK;
 }
 
@@ -509,8 +510,8 @@ extern "C" sdm_status sdm_batch_set_launch_config(sdm_batch* b, const sdm_launch
     sh.waves_per_block = cfg->waves_per_block;
     sh.xcd_remap = cfg->xcd_remap;
     sh.block_slots = cfg->block_slots;
-    if (!shape_valid(sh)) {
-        set_error("launch config out of range");
+    if (!shape_valid(sh) || cfg->block_split != 0) {
+        set_error("launch config out of range (block_split is for single runs)");
         return SDM_EINVAL;
     }
     return batch_apply_shape(b, sh);

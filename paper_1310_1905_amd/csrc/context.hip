@@ -283,7 +283,9 @@ static sdm_status enqueue_recycle(sdm_ctx* x)
 
 static sdm_status launch(sdm_ctx* x, const StepArgs& a, bool perm)
 {
-    return launch_step(x->stream, a, x->group_begin, x->group_end, x->n_groups, x->shape, false,
+    StepArgs b = a;
+    if (!perm && x->shape.block_split > 0 && x->grid.n_block > 0) b.split_epoch = ++x->grid.split_epoch;
+    return launch_step(x->stream, b, x->group_begin, x->group_end, x->n_groups, x->shape, false,
                        perm);
 }
 
@@ -569,6 +571,11 @@ extern "C" sdm_status sdm_get_stats(sdm_ctx* x, uint64_t* pair_tests, uint64_t* 
     }
     if (pair_tests) *pair_tests = p;
     if (collisions) *collisions = c;
+    if (h[kSplitTimeoutStat] != 0) {
+        set_error("%llu split-tier steps timed out waiting for their cell's workgroups; "
+                  "their results are not reliable", h[kSplitTimeoutStat]);
+        return SDM_EDEVICE;
+    }
     return SDM_OK;
 }
 
@@ -600,6 +607,7 @@ static LaunchShape from_cfg(const sdm_launch_config& c)
     s.waves_per_block = c.waves_per_block;
     s.xcd_remap = c.xcd_remap;
     s.block_slots = c.block_slots;
+    s.block_split = c.block_split;
     return s;
 }
 
@@ -610,6 +618,7 @@ static void to_cfg(const LaunchShape& s, sdm_launch_config* c)
     c->waves_per_block = s.waves_per_block;
     c->xcd_remap = s.xcd_remap;
     c->block_slots = s.block_slots;
+    c->block_split = s.block_split;
 }
 
 static sdm_status apply_shape(sdm_ctx* x, const LaunchShape& sh)
@@ -703,8 +712,10 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
                     c.xcd_remap = xr;
                     if (shape_valid(c)) cands.push_back(c);
                 }
-    // the wavefront-tier shapes first; then the workgroup-tier limit on the best of them
+    // the wavefront-tier shapes first; then the workgroup-tier limit on the best
+    // of them, then the split of its cells over several workgroups
     const size_t n_wave_cands = cands.size();
+    size_t n_block_cands = 0;
     hipEvent_t e0, e1;
     SDM_HIP(hipEventCreate(&e0));
     SDM_HIP(hipEventCreate(&e1));
@@ -717,6 +728,17 @@ extern "C" sdm_status sdm_autotune(sdm_ctx* x, void* scratch, size_t scratch_byt
                 if (bs == best.block_slots) continue;
                 LaunchShape c = best;
                 c.block_slots = bs;
+                c.block_split = 0;
+                if (shape_valid(c)) cands.push_back(c);
+            }
+            n_block_cands = cands.size();
+            if (ci == cands.size()) break;
+        }
+        if (ci == n_block_cands && x->grid.n_block > 0) {
+            for (uint32_t lg = 0; lg <= kSplitMaxLg; ++lg) {
+                if (lg == best.block_split) continue;
+                LaunchShape c = best;
+                c.block_split = lg;
                 if (shape_valid(c)) cands.push_back(c);
             }
             if (ci == cands.size()) break;

@@ -226,7 +226,8 @@ bool shape_valid(const LaunchShape& c)
     // sized for cells of more than 256 slots
     const bool block_ok = (c.block_slots == 0 && c.group_slots >= 256) ||
                           c.block_slots == kBlockSmall || c.block_slots == kBlockLarge;
-    return waves_ok && slots_ok && block_ok && c.groups_per_wave >= 1 &&
+    const bool split_ok = c.block_split <= kSplitMaxLg && (c.block_split == 0 || c.block_slots > 0);
+    return waves_ok && slots_ok && block_ok && split_ok && c.groups_per_wave >= 1 &&
            c.groups_per_wave <= 64 && c.xcd_remap <= 1;
 }
 
@@ -248,6 +249,7 @@ void carve_grid(Carver& c, uint64_t n_sd, uint32_t n_cells, GridArrays* g)
     // a workgroup-tier cell has more slots than the smallest group (64)
     g->cap_block = std::min<uint64_t>(n_cells, n_sd / 65 + 1);
     g->blist = c.take<uint32_t>(g->cap_block);
+    g->split_arrive = c.take<uint32_t>(g->cap_block);
 }
 
 sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
@@ -270,9 +272,12 @@ sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
         SDM_HIP(hipMemcpyAsync(g->gpchunk, plan.gpchunk.data(), plan.gpchunk.size() * sizeof(uint2),
                                hipMemcpyHostToDevice, s));
     }
-    if (!plan.block.empty())
+    if (!plan.block.empty()) {
         SDM_HIP(hipMemcpyAsync(g->blist, plan.block.data(), plan.block.size() * sizeof(uint32_t),
                                hipMemcpyHostToDevice, s));
+        SDM_HIP(hipMemsetAsync(g->split_arrive, 0, plan.block.size() * sizeof(uint32_t), s));
+    }
+    g->split_epoch = 0;
     g->n_block = static_cast<uint32_t>(plan.block.size());
     g->n_block_big = plan.block_big;
     g->n_grid = static_cast<uint32_t>(plan.grid.size());
@@ -297,15 +302,31 @@ void grid_args(const GridArrays& g, StepArgs* a)
     a->n_gpchunk = g.n_gpchunk;
     a->gtilesum = g.gtilesum;
     a->blist = g.blist;
+    a->split_arrive = g.split_arrive;
+    a->split_epoch = g.split_epoch;
     a->n_block = g.n_block;
     a->n_block_big = g.n_block_big;
 }
 
 // Workgroup tier: 1024-thread workgroups for the cells above kBlockSmall slots
-// (the head of the list), 256-thread ones for the rest.
+// (the head of the list), 256-thread ones for the rest.  In single runs with
+// split_lg > 0 every such cell takes 2^split_lg workgroups of the split tier
+// instead (a step launch needs a.split_epoch set by the caller: the number of
+// split-tier step launches since the plan was uploaded, this one included).
 template <bool BATCHED, bool PERM, bool PROBE>
-static sdm_status launch_block(hipStream_t s, const StepArgs& a)
+static sdm_status launch_block(hipStream_t s, const StepArgs& a, uint32_t split_lg)
 {
+    if (!BATCHED && split_lg > 0) {
+        if (split_lg > kSplitMaxLg || (static_cast<uint64_t>(a.n_block) << split_lg) > 0x7FFFFFFFull) {
+            set_error("too many split-tier workgroups for one launch");
+            return SDM_EINVAL;
+        }
+        const dim3 grid(a.n_block << split_lg);
+        hipLaunchKernelGGL((k_split_cells<kBlockLarge, 1024, PERM, PROBE>), grid, dim3(1024), 0, s,
+                           a, a.blist, split_lg);
+        SDM_LAUNCHED();
+        return SDM_OK;
+    }
     if (a.n_block_big > 0) {
         hipLaunchKernelGGL((k_block_cells<kBlockLarge, 1024, BATCHED, PERM, PROBE>),
                            dim3(a.n_block_big), dim3(1024), 0, s, a, a.blist);
@@ -422,7 +443,7 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
             a.xcd_remap = shape.xcd_remap;
             SDM_TRY(launch_wave_probe(s, a, n_groups, shape));
         }
-        if (base.n_block > 0) SDM_TRY((launch_block<false, false, true>(s, base)));
+        if (base.n_block > 0) SDM_TRY((launch_block<false, false, true>(s, base, shape.block_split)));
         if (base.n_grid > 0) SDM_TRY((launch_grid<false, false, true>(s, base)));
         return SDM_OK;
     }
@@ -440,9 +461,10 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
     }
     if (base.n_block > 0) {
         if (batched)
-            SDM_TRY(perm ? (launch_block<true, true, false>(s, base)) : (launch_block<true, false, false>(s, base)));
+            SDM_TRY(perm ? (launch_block<true, true, false>(s, base, 0)) : (launch_block<true, false, false>(s, base, 0)));
         else
-            SDM_TRY(perm ? (launch_block<false, true, false>(s, base)) : (launch_block<false, false, false>(s, base)));
+            SDM_TRY(perm ? (launch_block<false, true, false>(s, base, shape.block_split))
+                         : (launch_block<false, false, false>(s, base, shape.block_split)));
     }
     if (base.n_grid > 0) {
         if (batched)

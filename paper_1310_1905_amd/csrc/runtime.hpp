@@ -123,6 +123,7 @@ struct LaunchShape {
     uint32_t waves_per_block = 1;
     uint32_t xcd_remap = 0;
     uint32_t block_slots = kBlockLarge;   // largest cell of the workgroup tier (0: none)
+    uint32_t block_split = 0;   // single runs: 2^block_split workgroups per workgroup-tier cell
 };
 
 // Work lists of one step: wave-tier groups of consecutive cells and the
@@ -148,6 +149,8 @@ struct GridArrays {
     uint2* gpchunk = nullptr;
     uint32_t* gtilesum = nullptr;
     uint32_t* blist = nullptr;      // workgroup-tier cells
+    uint32_t* split_arrive = nullptr;   // split tier: arrival counters of those cells
+    uint32_t split_epoch = 0;       // split-tier steps since the counters were cleared
     uint64_t cap_cells = 0, cap_chunks = 0, cap_tiles = 0, cap_buckets = 0, cap_pchunks = 0;
     uint64_t cap_block = 0;
     uint32_t n_grid = 0, n_gchunk = 0, n_gtile = 0, n_gbucket = 0, n_gpchunk = 0;

@@ -107,6 +107,10 @@ struct StepArgs {
     const uint32_t* blist;
     uint32_t n_block;
     uint32_t n_block_big;
+    // split tier: per workgroup-tier cell, workgroups that have read its
+    // multiplicities (grows by 2^block_split a step), and the step's number
+    uint32_t* split_arrive;
+    uint32_t split_epoch;
     uint32_t* gtilesum;
 };
 
@@ -1349,6 +1353,349 @@ __global__ __launch_bounds__(T) void k_block_cells(const StepArgs a, const uint3
     }
     const uint32_t tot = block_sum<T>(coll, L.red);
     if (tid == 0) add_counts(a, BATCHED, j.inst, blockIdx.x, npairs, tot);
+}
+
+// ---------------------------------------------------------------------------
+// Split tier: a workgroup-tier cell spread over G = 2^lgG workgroups, for runs
+// with too few such cells to fill the chip one workgroup each.  Workgroup g
+// takes the live SDs whose key has g as its top lgG bits.  The order is by key
+// first, so these hold the consecutive sorted positions [P0, P0 + M), where P0
+// counts the live SDs of smaller digit.  Each workgroup draws all keys of its
+// cell (a quarter Philox call per slot) to find P0, its own M SDs and the
+// smallest (key, slot) above its digit: the partner of its last SD when that
+// one opens a pair.  It orders its own SDs exactly in LDS (one bucket pass on
+// the next key bits, scan, scatter, in-bucket rank, as the workgroup tier)
+// and tests the pairs whose first member it holds, writing changed SDs at once.
+// Every workgroup reads the multiplicities of the whole cell to tell live from
+// dead, and another workgroup's collisions only change that when a multiplicity
+// drops to zero: such writes wait until every workgroup of the cell has counted
+// itself in after reading (a per-cell counter that grows by G each step; the
+// wait is bounded, and a time-out is counted and reported by sdm_get_stats).
+// Same order and results as the other tiers.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSplitMaxLg = 5;   // at most 32 workgroups per cell
+constexpr uint32_t kSplitSpinLimit = 1u << 20;   // about a second of polling
+// Index of the split-tier time-out counter within the first counter slot.
+constexpr int kSplitTimeoutStat = 3;
+
+template <int CAPB, int T>
+struct SplitLds {
+    static_assert(CAPB <= 65536, "slots are 16-bit");
+    union {
+        struct {
+            uint64_t kv[CAPB + 1];      // own (key << 32 | slot) grouped by sub-bucket; [CAPB] a dummy
+            uint32_t start[CAPB + 1];   // sub-bucket counts, then starts; start[nb] = M
+        } sort;
+        struct {
+            uint64_t xi[CAPB + 1];      // own SDs in sorted order, then the last one's partner
+            double r[CAPB + 1];
+        } pairs;
+    };
+    uint16_t slot[CAPB + 1];
+    uint32_t red[3 * (T / kWave)];
+    uint64_t low[T / kWave];
+    double dmax[T / kWave];
+    uint64_t partner_xi;                // the partner's multiplicity and radius
+    double partner_r;
+    uint16_t zero[CAPB / 2 + 1];        // slots whose multiplicity drops to zero
+    uint32_t ncoll;
+    uint32_t nzero;
+};
+
+template <int CAPB, int T, bool PERM, bool PROBE = false>
+__global__ __launch_bounds__(T) void k_split_cells(const StepArgs a, const uint32_t* list,
+                                                   uint32_t lgG)
+{
+    constexpr int Q = CAPB / (4 * T);   // key calls per thread, four slots each
+    constexpr int S = 4 * Q;
+    constexpr int W = T / kWave;
+    static_assert(CAPB % (4 * T) == 0 && T % kWave == 0, "split shape");
+    static_assert(!(PERM && PROBE), "one mode");
+    __shared__ SplitLds<CAPB, T> L;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const uint32_t part = blockIdx.x & ((1u << lgG) - 1u);
+    const uint32_t c = load_const_u32(list, blockIdx.x >> lgG);
+    const CellJob j = resolve_cell<false>(a, c);
+    const uint32_t n = j.n_slots;   // <= CAPB, > 2^(lgG + 1)
+    const uint32_t item = blockIdx.x >> lgG;
+    if (tid == 0) {
+        L.ncoll = 0;
+        L.nzero = 0;
+    }
+
+    // (1) the keys, multiplicities and radii of all slots of the cell (thread t
+    // holds the four slots of calls t, t + T, ...)
+    uint32_t key[S];
+    uint64_t xv[S];
+    double rv[S];
+    bool own[S];
+    uint32_t below = 0, mine = 0, above = 0;
+    uint64_t low = ~0ull;   // smallest (key, slot) above the own digit
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const uint32_t q = tid + static_cast<uint32_t>(i) * T;
+        Words4 w = {{0u, 0u, 0u, 0u}};
+        if (4 * q < n) w = philox4x32_10(q, j.rng_cell, j.step, kTagShuffle, j.k0, j.k1);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 4 * i + t;
+            const uint32_t s = 4 * q + static_cast<uint32_t>(t);
+            xv[k] = s < n ? a.xi[j.off + s] : 0u;
+            rv[k] = 0.0;
+            if constexpr (!PERM) rv[k] = s < n ? a.r[j.off + s] : 0.0;
+            key[k] = w.w[t];
+            const uint32_t d = bucket_of(key[k], lgG);
+            const bool live = xv[k] != 0u;
+            own[k] = live && d == part;
+            below += (live && d < part) ? 1u : 0u;
+            mine += own[k] ? 1u : 0u;
+            if (live && d > part) {
+                ++above;
+                const uint64_t v = (static_cast<uint64_t>(key[k]) << 32) | s;
+                low = v < low ? v : low;
+            }
+        }
+    }
+    // (2) block totals: P0, M, the live SDs above, and the partner candidate
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        below += __shfl_xor(below, d, kWave);
+        mine += __shfl_xor(mine, d, kWave);
+        above += __shfl_xor(above, d, kWave);
+        const uint64_t o = __shfl_xor(low, d, kWave);
+        low = o < low ? o : low;
+    }
+    if (lane == 0) {
+        L.red[wv] = below;
+        L.red[W + wv] = mine;
+        L.red[2 * W + wv] = above;
+        L.low[wv] = low;
+    }
+    __syncthreads();
+    uint32_t P0 = 0, M = 0, A = 0;
+    uint64_t partner = ~0ull;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        P0 += L.red[w];
+        M += L.red[W + w];
+        A += L.red[2 * W + w];
+        partner = L.low[w] < partner ? L.low[w] : partner;
+    }
+    const uint32_t n_live = P0 + M + A;
+    const uint32_t npairs = n_live >> 1;
+    // every thread's reads of the cell's multiplicities are complete here
+    if constexpr (!PERM && !PROBE) {
+        if (tid == 0) __hip_atomic_fetch_add(a.split_arrive + item, 1u, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if constexpr (!PERM) {
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const uint32_t s = 4 * (tid + static_cast<uint32_t>(k / 4) * T) + static_cast<uint32_t>(k % 4);
+            if (A > 0 && xv[k] != 0u && ((static_cast<uint64_t>(key[k]) << 32) | s) == partner) {
+                L.partner_xi = xv[k];
+                L.partner_r = rv[k];
+            }
+        }
+    }
+    // pairs m with 2m in [P0, P0 + M) and 2m + 1 < n_live
+    const uint32_t m_lo = (P0 + 1u) >> 1;
+    const uint32_t m_end = min((P0 + M + 1u) >> 1, npairs);
+    if (M == 0) {
+        if constexpr (PERM) {
+            if (tid == 0 && part == 0) a.nlive_out[c] = n_live;
+        } else if constexpr (!PROBE) {
+            if (tid == 0 && part == 0) add_counts(a, false, 0, blockIdx.x, npairs, 0);
+        }
+        return;
+    }
+    const uint32_t lg = 31u - static_cast<uint32_t>(__clz(static_cast<int>(M)));
+    const uint32_t nb = 1u << lg;
+    for (uint32_t i = tid; i <= nb; i += T) L.sort.start[i] = 0;
+    __syncthreads();
+
+    // (3) sub-bucket counts on the lg key bits after the digit
+    uint32_t bkt[S], arr[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        bkt[k] = 0;
+        arr[k] = 0;
+        if (own[k]) {
+            bkt[k] = bucket_of(key[k] << lgG, lg);
+            arr[k] = atomicAdd(&L.sort.start[bkt[k]], 1u);
+        }
+    }
+    __syncthreads();
+    {
+        const uint32_t per = (nb + T - 1) / T;
+        const uint32_t b0 = tid * per;
+        const uint32_t b1 = b0 + per < nb ? b0 + per : nb;
+        uint32_t run = 0;
+        for (uint32_t b = b0; b < b1; ++b) run += L.sort.start[b];
+        const uint32_t incl = wave_inclusive_sum_dpp(run);
+        if (lane == kWave - 1) L.red[wv] = incl;
+        __syncthreads();
+        uint32_t before = incl - run;
+#pragma unroll
+        for (int w = 0; w < W; ++w) before += static_cast<uint32_t>(w) < wv ? L.red[w] : 0u;
+        for (uint32_t b = b0; b < b1; ++b) {
+            const uint32_t cnt = L.sort.start[b];
+            L.sort.start[b] = before;
+            before += cnt;
+        }
+        if (tid == 0) L.sort.start[nb] = M;
+    }
+    __syncthreads();
+
+    // (4) scatter, then the rank inside each sub-bucket: own sorted positions.
+    // Branch-free over the thread's slots (others go to the dummy entry), so
+    // that the LDS accesses of all of them are in flight together.
+    uint64_t me[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const uint32_t s = 4 * (tid + static_cast<uint32_t>(k / 4) * T) + static_cast<uint32_t>(k % 4);
+        me[k] = (static_cast<uint64_t>(key[k]) << 32) | s;
+    }
+    {
+        uint32_t dst[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const uint32_t b = L.sort.start[bkt[k]];
+            dst[k] = own[k] ? b + arr[k] : static_cast<uint32_t>(CAPB);
+        }
+#pragma unroll
+        for (int k = 0; k < S; ++k) L.sort.kv[dst[k]] = me[k];
+    }
+    __syncthreads();
+    uint32_t pos[S];
+    {
+        uint32_t len[S], rank[S];
+        uint32_t longest = 0;
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            pos[k] = L.sort.start[bkt[k]];
+            const uint32_t hi = L.sort.start[bkt[k] + 1];
+            len[k] = own[k] ? hi - pos[k] : 0u;
+            longest = len[k] > longest ? len[k] : longest;
+            rank[k] = 0;
+        }
+        for (uint32_t t = 0; t < longest; ++t) {
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                const bool in = t < len[k];
+                const uint64_t v = L.sort.kv[in ? pos[k] + t : static_cast<uint32_t>(CAPB)];
+                rank[k] += (in && v < me[k]) ? 1u : 0u;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < S; ++k) pos[k] += rank[k];
+    }
+    if constexpr (PERM) {
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            if (own[k]) {
+                const uint32_t s = 4 * (tid + static_cast<uint32_t>(k / 4) * T) + static_cast<uint32_t>(k % 4);
+                a.perm_out[j.off + P0 + pos[k]] = s;
+            }
+        }
+        if (tid == 0 && part == 0) a.nlive_out[c] = n_live;
+        return;
+    }
+    __syncthreads();   // the sort arrays are overwritten below
+
+    // (5) own SDs in sorted order, and at M the partner of the last one
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        if (own[k]) {
+            const uint32_t s = 4 * (tid + static_cast<uint32_t>(k / 4) * T) + static_cast<uint32_t>(k % 4);
+            L.pairs.xi[pos[k]] = xv[k];
+            L.pairs.r[pos[k]] = rv[k];
+            L.slot[pos[k]] = static_cast<uint16_t>(s);
+        }
+    }
+    if (tid == 0 && A > 0) {
+        L.pairs.xi[M] = L.partner_xi;
+        L.pairs.r[M] = L.partner_r;
+        L.slot[M] = static_cast<uint16_t>(partner);
+    }
+    __syncthreads();
+
+    // (6) pair tests, one thread per own pair (the two pairs of a uniform call
+    // draw it twice: a workgroup's pairs are few, and this halves each thread's
+    // chain); changed SDs are written at once, zero multiplicities later
+    const double scale = npairs ? upscale_factor_small(n_live) : 0.0;
+    double best = 0.0;
+    for (uint32_t m = m_lo + tid; m < m_end; m += T) {
+        const Words4 w = philox4x32_10(m >> 1, j.rng_cell, j.step, kTagUniform, j.k0, j.k1);
+        const uint32_t ia = 2 * m - P0, ib = ia + 1;   // ib <= M
+        const uint64_t xa = L.pairs.xi[ia], xb = L.pairs.xi[ib];
+        const double ra = L.pairs.r[ia], rb = L.pairs.r[ib];
+        const double K = collection_kernel(j.kernel, j.kp, ra, rb);
+        const bool a_is_j = xa >= xb;
+        PairState st;
+        st.xj = a_is_j ? xa : xb;
+        st.xk = a_is_j ? xb : xa;
+        st.rj = a_is_j ? ra : rb;
+        st.rk = a_is_j ? rb : ra;
+        const double p = collision_probability(st.xj, K, j.dt, j.dV, scale);
+        if constexpr (PROBE) {
+            best = fmax(best, p);
+            continue;
+        }
+        const double u = (m & 1u) ? uniform_open01(w.w[2], w.w[3]) : uniform_open01(w.w[0], w.w[1]);
+        const bool release = (a.rules & kRuleRelease) != 0;
+        const uint64_t g = release ? collision_count_release(p, u) : collision_count(p, u, st.xj, st.xk);
+        if (g == 0) continue;
+        apply_collisions(g, st, release);
+        const uint32_t sa = L.slot[ia], sb = L.slot[ib];
+        const uint64_t gj = static_cast<uint64_t>(j.off) + (a_is_j ? sa : sb);
+        const uint64_t gk = static_cast<uint64_t>(j.off) + (a_is_j ? sb : sa);
+        if (st.xj != 0u) a.xi[gj] = st.xj;
+        else L.zero[atomicAdd(&L.nzero, 1u)] = static_cast<uint16_t>(a_is_j ? sa : sb);
+        a.r[gk] = st.rk;
+        if (st.j_changed_r) {
+            a.xi[gk] = st.xk;
+            a.r[gj] = st.rj;
+        }
+        update_dry(a, g, gj, gk, st.j_changed_r);
+        atomicAdd(&L.ncoll, 1u);
+    }
+    if constexpr (PROBE) {
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) best = fmax(best, __shfl_xor(best, d, kWave));
+        if (lane == 0) L.dmax[wv] = best;
+        __syncthreads();
+        if (tid == 0) {
+            double b = L.dmax[0];
+            for (int w = 1; w < W; ++w) b = fmax(b, L.dmax[w]);
+            if (b > 0.0)
+                atomicMax(reinterpret_cast<unsigned long long*>(a.cell_max + c),
+                          static_cast<unsigned long long>(__double_as_longlong(b)));
+        }
+        return;
+    }
+    __syncthreads();
+    if (L.nzero > 0) {
+        // every workgroup of the cell has read the multiplicities once the
+        // counter reaches G times the number of this cell's split steps so far
+        if (tid == 0) {
+            const uint32_t target = a.split_epoch << lgG;
+            uint32_t spins = 0;
+            while (static_cast<int32_t>(__hip_atomic_load(a.split_arrive + item, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+                if (++spins == kSplitSpinLimit) {
+                    atomicAdd(a.stats + kSplitTimeoutStat, 1ull);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < L.nzero; i += T) a.xi[static_cast<uint64_t>(j.off) + L.zero[i]] = 0u;
+    }
+    if (tid == 0) add_counts(a, false, 0, blockIdx.x, part == 0 ? npairs : 0u, L.ncoll);
 }
 
 }  // namespace sdm

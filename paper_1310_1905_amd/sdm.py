@@ -35,7 +35,7 @@ class KernelParams(ctypes.Structure):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("group_slots", _u32), ("groups_per_wave", _u32), ("waves_per_block", _u32),
-                ("xcd_remap", _u32), ("block_slots", _u32)]
+                ("xcd_remap", _u32), ("block_slots", _u32), ("block_split", _u32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
