@@ -149,7 +149,10 @@ sdm_status sdm_get_state(sdm_ctx *ctx, uint64_t *xi_out, double *r_out);
  * cell and step of which eq. (P_ij) speaks (n live particles), summed over
  * cells and steps; and collisions, the examined pairs with at least one
  * collision event (Sect. 5.1.4).  host outputs, nullable.
- * Synchronises the stream.  Errors: SDM_EINVAL (ctx NULL), SDM_EDEVICE. */
+ * Synchronises the stream.  Errors: SDM_EINVAL (ctx NULL), SDM_EDEVICE (also
+ * when a split-tier step, launch knob block_split, timed out waiting for the
+ * other workgroups of a cell: the outputs are filled, but the state of those
+ * steps is not reliable). */
 sdm_status sdm_get_stats(sdm_ctx *ctx, uint64_t *pair_tests, uint64_t *collisions);
 
 /* Storage-order views for diagnostics: slot offsets (dev uint32[n_cells+1])
