@@ -47,6 +47,18 @@ KERNEL_SOURCES = ["paper_1310_1905_amd/csrc/step_kernels.hpp",
                   "paper_1310_1905_amd/csrc/device_math.hpp"]
 
 
+LAUNCH_FIELDS = ("group_slots", "groups_per_wave", "waves_per_block", "xcd_remap",
+                 "block_slots", "block_split")
+
+
+def launch_fields(text: str) -> dict:
+    """--launch value (comma-separated, in LAUNCH_FIELDS order, a prefix of them) as keywords."""
+    vals = [int(v) for v in text.split(",")]
+    if not 1 <= len(vals) <= len(LAUNCH_FIELDS):
+        raise SystemExit(f"--launch takes 1 to {len(LAUNCH_FIELDS)} values")
+    return dict(zip(LAUNCH_FIELDS, vals))
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -145,6 +157,20 @@ def cpu_baseline(pop, n_cells_sample: int, steps: int, single_cells: int):
             "cpu_model": _cpu_model(), "host_cpus_visible": os.cpu_count()}
 
 
+def calibration_copy(gib: float) -> int:
+    """Three plain device copies of `gib` GiB, for scaling the HBM byte counters of a
+    profile run; returns the bytes of one copy."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    return 8 * n
+
+
 def bench_large(args):
     import torch
 
@@ -156,9 +182,7 @@ def bench_large(args):
     stream = torch.cuda.Stream()
     ctx = sdm.Context(pop.cell, pop.xi, pop.r, pop.dV, stream=stream)
     if args.launch:
-        slots, gpw, wpb, xr = (int(v) for v in args.launch.split(","))
-        ctx.set_launch_config(group_slots=slots, groups_per_wave=gpw, waves_per_block=wpb,
-                              xcd_remap=xr)
+        ctx.set_launch_config(**launch_fields(args.launch))
     elif args.autotune:
         best = ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=3)
         log(f"autotuned launch config {best.as_dict()}")
@@ -207,15 +231,7 @@ def bench_large(args):
     del ctx
     torch.cuda.empty_cache()
     if args.calib_copy_gib > 0:
-        # plain copy of known size, for scaling the HBM byte counters of a profile run
-        n = int(args.calib_copy_gib * (1 << 30)) // 8
-        a = torch.ones(n, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        out["calibration_copy_bytes"] = 8 * n
-        del a, b
+        out["calibration_copy_bytes"] = calibration_copy(args.calib_copy_gib)
     if args.cpu_baseline:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(pop, args.cpu_cells, args.cpu_steps, args.cpu_cells_1t)
@@ -249,7 +265,8 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=64.0, help="served HBM budget")
     ap.add_argument("--launch", default="",
                     help="fixed launch config group_slots,groups_per_wave,waves_per_block,"
-                         "xcd_remap (skips the autotuner)")
+                         "xcd_remap[,block_slots[,block_split]] for the large domain, the box "
+                         "and the 2D domain (skips their autotuner)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "only one GPU is supported: the coalescence step would "
@@ -264,6 +281,8 @@ def main():
     else:
         from paper_1310_1905_amd import bench_workloads
         out = bench_workloads.run(args)
+        if args.calib_copy_gib > 0:
+            out["calibration_copy_bytes"] = calibration_copy(args.calib_copy_gib)
     print(json.dumps(out), flush=True)
 
 

@@ -42,7 +42,11 @@ def _line(args, value, ms_per_step, workload, extra=None, unit="pair tests/s"):
 def _single(args, pop, workload):
     stream = torch.cuda.Stream()
     ctx = sdm.Context(pop.cell, pop.xi, pop.r, pop.dV, stream=stream)
-    if getattr(args, "autotune", True):
+    if getattr(args, "launch", ""):
+        fields = ("group_slots", "groups_per_wave", "waves_per_block", "xcd_remap",
+                  "block_slots", "block_split")
+        ctx.set_launch_config(**dict(zip(fields, (int(v) for v in args.launch.split(",")))))
+    elif getattr(args, "autotune", True):
         ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=5)
     for t in range(args.warmup):
         ctx.step(pop.dt, pop.kernel, pop.seed, t)
@@ -67,7 +71,12 @@ def run_ensemble(args):
     log(f"ensemble: {len(pops)} instances, {n_sd} SDs")
     b = sdm.Batch(n_sd, len(pops), len(pops))
     handles = [b.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, p.seed) for p in pops]
-    launch = b.autotune(reps=3).as_dict() if getattr(args, "autotune", True) else None
+    if getattr(args, "launch", ""):
+        fields = ("group_slots", "groups_per_wave", "waves_per_block", "xcd_remap", "block_slots")
+        b.set_launch_config(**dict(zip(fields, (int(v) for v in args.launch.split(",")[:5]))))
+        launch = b.launch_config().as_dict()
+    else:
+        launch = b.autotune(reps=3).as_dict() if getattr(args, "autotune", True) else None
     log(f"ensemble: batch launch config {b.launch_config().as_dict()}")
     for _ in range(args.warmup):
         b.step(use_graph=True)
