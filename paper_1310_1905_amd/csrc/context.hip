@@ -283,10 +283,16 @@ static sdm_status enqueue_recycle(sdm_ctx* x)
 
 static sdm_status launch(sdm_ctx* x, const StepArgs& a, bool perm)
 {
+    // a split-tier step counts itself in once its kernel is enqueued: the
+    // device counters then grow by 2^block_split per cell
     StepArgs b = a;
-    if (!perm && x->shape.block_split > 0 && x->grid.n_block > 0) b.split_epoch = ++x->grid.split_epoch;
-    return launch_step(x->stream, b, x->group_begin, x->group_end, x->n_groups, x->shape, false,
-                       perm);
+    const bool split = !perm && x->shape.block_split > 0 && x->grid.n_block > 0;
+    if (split) b.split_epoch = x->grid.split_epoch + 1;
+    bool enqueued = false;
+    const sdm_status st = launch_step(x->stream, b, x->group_begin, x->group_end, x->n_groups,
+                                      x->shape, false, perm, false, &enqueued);
+    if (split && enqueued) x->grid.split_epoch = b.split_epoch;
+    return st;
 }
 
 extern "C" sdm_status sdm_coalesce_step(sdm_ctx* x, double dt, sdm_kernel kernel, uint64_t seed,

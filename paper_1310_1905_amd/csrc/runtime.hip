@@ -312,9 +312,11 @@ void grid_args(const GridArrays& g, StepArgs* a)
 // (the head of the list), 256-thread ones for the rest.  In single runs with
 // split_lg > 0 every such cell takes 2^split_lg workgroups of the split tier
 // instead (a step launch needs a.split_epoch set by the caller: the number of
-// split-tier step launches since the plan was uploaded, this one included).
+// split-tier step launches since the plan was uploaded, this one included; the
+// caller counts the launch when *split_enqueued comes back true).
 template <bool BATCHED, bool PERM, bool PROBE>
-static sdm_status launch_block(hipStream_t s, const StepArgs& a, uint32_t split_lg)
+static sdm_status launch_block(hipStream_t s, const StepArgs& a, uint32_t split_lg,
+                               bool* split_enqueued)
 {
     if (!BATCHED && split_lg > 0) {
         if (split_lg > kSplitMaxLg || (static_cast<uint64_t>(a.n_block) << split_lg) > 0x7FFFFFFFull) {
@@ -325,6 +327,7 @@ static sdm_status launch_block(hipStream_t s, const StepArgs& a, uint32_t split_
         hipLaunchKernelGGL((k_split_cells<kBlockLarge, 1024, PERM, PROBE>), grid, dim3(1024), 0, s,
                            a, a.blist, split_lg);
         SDM_LAUNCHED();
+        if (split_enqueued) *split_enqueued = true;
         return SDM_OK;
     }
     if (a.n_block_big > 0) {
@@ -427,7 +430,7 @@ static sdm_status launch_wave_probe(hipStream_t s, const StepArgs& a, uint32_t n
 
 sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* group_begin,
                        const uint32_t* group_end, uint32_t n_groups, const LaunchShape& shape,
-                       bool batched, bool perm, bool probe)
+                       bool batched, bool perm, bool probe, bool* split_enqueued)
 {
     if (probe) {
         if (batched || perm) {
@@ -443,7 +446,7 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
             a.xcd_remap = shape.xcd_remap;
             SDM_TRY(launch_wave_probe(s, a, n_groups, shape));
         }
-        if (base.n_block > 0) SDM_TRY((launch_block<false, false, true>(s, base, shape.block_split)));
+        if (base.n_block > 0) SDM_TRY((launch_block<false, false, true>(s, base, shape.block_split, split_enqueued)));
         if (base.n_grid > 0) SDM_TRY((launch_grid<false, false, true>(s, base)));
         return SDM_OK;
     }
@@ -461,10 +464,10 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
     }
     if (base.n_block > 0) {
         if (batched)
-            SDM_TRY(perm ? (launch_block<true, true, false>(s, base, 0)) : (launch_block<true, false, false>(s, base, 0)));
+            SDM_TRY(perm ? (launch_block<true, true, false>(s, base, 0, nullptr)) : (launch_block<true, false, false>(s, base, 0, nullptr)));
         else
-            SDM_TRY(perm ? (launch_block<false, true, false>(s, base, shape.block_split))
-                         : (launch_block<false, false, false>(s, base, shape.block_split)));
+            SDM_TRY(perm ? (launch_block<false, true, false>(s, base, shape.block_split, split_enqueued))
+                         : (launch_block<false, false, false>(s, base, shape.block_split, split_enqueued)));
     }
     if (base.n_grid > 0) {
         if (batched)

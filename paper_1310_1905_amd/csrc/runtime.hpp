@@ -175,9 +175,11 @@ void plan_finish(Plan& plan);
 // grid-tier arrays, see grid_args).
 // probe: instead of the collisions, the largest P_ij of every cell goes to
 // base.cell_max (single runs only; grid-tier entries must start at 0).
+// *split_enqueued (nullable) becomes true once a split-tier kernel is enqueued.
 sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* group_begin,
                        const uint32_t* group_end, uint32_t n_groups, const LaunchShape& shape,
-                       bool batched, bool perm, bool probe = false);
+                       bool batched, bool perm, bool probe = false,
+                       bool* split_enqueued = nullptr);
 
 bool shape_valid(const LaunchShape& sh);
 
