@@ -538,6 +538,16 @@ sdm_status sdm_coalesce_sorted_static(void *stream, uint64_t n_sd, uint32_t n_ce
 sdm_status sdm_debug_philox(void *stream, uint64_t n, const uint32_t *ctr, const uint32_t *key,
                             uint32_t *out);
 
+/* The bounded wait of the split tier (launch knob block_split), for tests of its
+ * time-out path: spin_limit sets how many polls a wait makes before it gives up
+ * (0 restores the default, about a second), and epoch_skew is added to the
+ * context's count of split-tier steps, so that the following steps wait for
+ * arrivals that never come; each of their zero-multiplicity writes then gives up
+ * after spin_limit polls, writes anyway and is counted, and sdm_get_stats
+ * returns SDM_EDEVICE.  A later re-plan (a launch config with other
+ * group_slots or block_slots) clears the skew.  Errors: SDM_EINVAL (ctx NULL). */
+sdm_status sdm_debug_split_wait(sdm_ctx *ctx, uint32_t spin_limit, uint32_t epoch_skew);
+
 /* Philox4x32-10 over a counter range: out[4i..4i+3] (dev uint32[4n]) =
  * Philox(counter = (counter[0] + lo32(i), counter[1] + hi32(i), counter[2],
  * counter[3]), key = (key[0], key[1])), words modulo 2^32; counter and key are

@@ -78,6 +78,7 @@ StepArgs base_args(const sdm_ctx* x)
     a.off_begin = x->offsets;
     a.off_end = x->offsets + 1;
     a.dV = x->dV;
+    a.split_spin_limit = x->split_spin_limit;
     a.kp = to_kp(x->params);
     a.rules = x->rules;
     a.rd3 = x->rd3;
@@ -308,6 +309,14 @@ extern "C" sdm_status sdm_coalesce_step(sdm_ctx* x, double dt, sdm_kernel kernel
         SDM_TRY(step_args(x, dt, kernel, seed, step, &a));
     }
     return launch(x, a, false);
+}
+
+extern "C" sdm_status sdm_debug_split_wait(sdm_ctx* x, uint32_t spin_limit, uint32_t epoch_skew)
+{
+    SDM_TRY(check_ctx(x));
+    x->split_spin_limit = spin_limit;
+    x->grid.split_epoch += epoch_skew;
+    return SDM_OK;
 }
 
 extern "C" sdm_status sdm_debug_permutation(sdm_ctx* x, uint64_t seed, uint64_t step,

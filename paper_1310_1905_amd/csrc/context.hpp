@@ -50,6 +50,7 @@ struct sdm_ctx {
     double* dV = nullptr;
     uint32_t* group_begin = nullptr;
     uint32_t* group_end = nullptr;
+    uint32_t split_spin_limit = 0;       // split-tier poll limit (0: the default)
     sdm::GridArrays grid;
     unsigned long long* stats = nullptr;
     unsigned int* err = nullptr;

@@ -111,6 +111,7 @@ struct StepArgs {
     // multiplicities (grows by 2^block_split a step), and the step's number
     uint32_t* split_arrive;
     uint32_t split_epoch;
+    uint32_t split_spin_limit;    // polls before a wait gives up (0: kSplitSpinLimit)
     uint32_t* gtilesum;
 };
 
@@ -1682,10 +1683,11 @@ __global__ __launch_bounds__(T) void k_split_cells(const StepArgs a, const uint3
         // counter reaches G times the number of this cell's split steps so far
         if (tid == 0) {
             const uint32_t target = a.split_epoch << lgG;
+            const uint32_t limit = a.split_spin_limit ? a.split_spin_limit : kSplitSpinLimit;
             uint32_t spins = 0;
             while (static_cast<int32_t>(__hip_atomic_load(a.split_arrive + item, __ATOMIC_RELAXED,
                                                           __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
-                if (++spins == kSplitSpinLimit) {
+                if (++spins >= limit) {
                     atomicAdd(a.stats + kSplitTimeoutStat, 1ull);
                     break;
                 }

@@ -76,6 +76,7 @@ def lib() -> ctypes.CDLL:
         "sdm_get_stats": (ctypes.c_int, [_P, _P, _P]),
         "sdm_get_layout": (ctypes.c_int, [_P, _P, _P]),
         "sdm_debug_permutation": (ctypes.c_int, [_P, _u64, _u64, _P, _P]),
+        "sdm_debug_split_wait": (ctypes.c_int, [_P, _u32, _u32]),
         "sdm_get_plan": (ctypes.c_int, [_P, _P, _P, _P, _P]),
         "sdm_set_rules": (ctypes.c_int, [_P, _u32]),
         "sdm_get_rules": (ctypes.c_int, [_P, _P]),
@@ -382,6 +383,11 @@ class Context:
         _check(lib().sdm_debug_permutation(self._ctx, int(seed), int(step), _dptr(order),
                                            _dptr(nlive)), "sdm_debug_permutation")
         return order[: self.n_sd], nlive[: self.n_cells]
+
+    def debug_split_wait(self, spin_limit: int, epoch_skew: int = 0):
+        """Test hook of the split tier's bounded wait (see sdm_debug_split_wait)."""
+        _check(lib().sdm_debug_split_wait(self._ctx, int(spin_limit), int(epoch_skew)),
+               "sdm_debug_split_wait")
 
     def plan(self):
         """(wave-tier groups, cells in them, workgroup-tier cells, grid-tier cells)."""

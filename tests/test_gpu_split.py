@@ -1,14 +1,15 @@
 """Parity of the split tier (a workgroup-tier cell spread over 2^block_split
-workgroups by the top key bits, changed pairs written by a second launch) with
-the FP64 oracle, through the C ABI.
+workgroups by the top key bits; changed SDs written at once, multiplicities that
+drop to zero once every workgroup of the cell has read) with the FP64 oracle,
+through the C ABI.
 
 Bar: pairing order, multiplicities, radii, dry attributes, counters and the
 per-cell probe maxima all bit-exact.  Cases: cells of 65 to 8192 slots with dead
 slots and every split from 2 to 32 workgroups (so that digits with no live SD,
 and cells where one workgroup holds every live SD, occur); the release rules
 with dry attributes, where equal multiplicities leave slots empty within the
-step; the 8192-SD Golovin box over many steps; and the rule that batches take
-no split.
+step; the 8192-SD Golovin box over many steps; the rule that batches take no
+split; and the time-out path of the wait, forced from the host.
 """
 import numpy as np
 import pytest
@@ -127,3 +128,33 @@ def test_split_rejected_where_it_does_not_apply(sdm_mod):
     assert e.value.status == -1
     assert b.launch_config().block_split == 0
     b.close()
+
+
+def test_split_wait_time_out_is_reported(sdm_mod, oracle_mod):
+    """The time-out path of the zero-multiplicity wait, forced from the host: the
+    context's split-step count is skewed so that the wait's target is never met,
+    with a poll limit of 64.  Steps still finish (every wait gives up), the writes
+    happen anyway, so the state equals the oracle's here (all workgroups had in fact
+    read long before), and sdm_get_stats reports the time-outs as an error."""
+    g = np.random.default_rng(31)
+    sizes = [3000, 5000]
+    cell, xi, r, dV = _cells(g, sizes, dead=0.0, xi_hi=2)      # all xi = 1: zeros every step
+    dV = dV * 1e-7
+    ctx = sdm_mod.Context(cell, xi, r, dV)
+    ctx.set_rules(RELEASE)
+    ctx.set_launch_config(group_slots=256, block_slots=8192, block_split=2)
+    ref = oracle_mod.SlotState(cell, xi, r, dV)
+    ctx.step(1.0, "geometric", 9, 0)
+    ref.step(1.0, oracle_mod.GEOMETRIC, 9, 0, rules=oracle_mod.RULE_FIDELITY)
+    assert ctx.stats() == (int(ref.stats[0]), int(ref.stats[1]))   # no time-out yet
+    ctx.debug_split_wait(64, epoch_skew=1000)
+    for t in range(1, 3):
+        ctx.step(1.0, "geometric", 9, t)
+        ref.step(1.0, oracle_mod.GEOMETRIC, 9, t, rules=oracle_mod.RULE_FIDELITY)
+    with pytest.raises(sdm_mod.SdmError) as e:
+        ctx.stats()
+    assert e.value.status == -3 and "timed out" in str(e.value)
+    xi_g, r_g = ctx.state_numpy()
+    xi_o, r_o = ref.input_order()
+    assert np.array_equal(xi_g, xi_o) and _bits_equal(r_g, r_o)
+    assert np.count_nonzero(xi_o == 0) > 0
