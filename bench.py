@@ -25,6 +25,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -60,10 +61,13 @@ def launch_fields(text: str) -> dict:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the step-kernel sources with // comments and blank lines removed, so
+    that a profile stays matched to the code it measured across comment edits."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p)) as f:
+            lines = (re.sub(r"//.*$", "", x).rstrip() for x in f.read().splitlines())
+        h.update("\n".join(x for x in lines if x).encode())
     return h.hexdigest()[:16]
 
 

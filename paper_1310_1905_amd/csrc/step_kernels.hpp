@@ -14,13 +14,16 @@
 // entries on average, so the sort is O(n) and its result is independent of
 // the atomic arrival order.
 //
-// Two tiers cover all cell sizes with identical results:
+// Four tiers cover all cell sizes with identical results:
 //   k_wave_groups -- one 64-lane wavefront per group of consecutive cells
 //                    (at most CAP storage slots in all), everything in LDS;
-//   grid tier     -- cells with more slots than a group holds, each spread
-//                    over many workgroups, with the sort arrays in a global
-//                    scratch area that is indexed like the super-droplet
-//                    arrays (a two-level digit sort, see below).
+//   k_block_cells -- one workgroup per cell of up to kBlockLarge slots, the
+//                    whole cell in LDS;
+//   k_split_cells -- such a cell spread over 2^lgG workgroups, one digit of
+//                    the top key bits each (single runs with few such cells);
+//   grid tier     -- larger cells, each spread over many workgroups, with the
+//                    sort arrays in a global scratch area that is indexed like
+//                    the super-droplet arrays (a two-level digit sort, see below).
 #pragma once
 
 #include "device_math.hpp"
