@@ -213,7 +213,6 @@ void plan_finish(Plan& plan)
         for (uint64_t s0 = 0; s0 < n; s0 += 1u << gc.lgc)
             plan.gchunk.push_back(make_uint2(i, static_cast<uint32_t>(s0)));
         for (uint32_t d = 0; d < (1u << gc.cb); ++d) plan.gbucket.push_back(make_uint2(i, d));
-        for (uint32_t y = 0; y < n / 2; y += kGridPairChunk) plan.gpchunk.push_back(make_uint2(i, y));
     }
 }
 
@@ -239,12 +238,10 @@ void carve_grid(Carver& c, uint64_t n_sd, uint32_t n_cells, GridArrays* g)
     g->cap_tiles = n_sd / kGridTile + g->cap_cells;
     // 2^cb <= 2^(ceil(log2 N) - 10) < N / 512
     g->cap_buckets = n_sd / (1u << (kGridBucketLg - 1)) + g->cap_cells;
-    g->cap_pchunks = n_sd / 2 / kGridPairChunk + g->cap_cells;
     g->gcell = c.take<GridCell>(g->cap_cells);
     g->gchunk = c.take<uint2>(g->cap_chunks);
     g->gtile = c.take<uint2>(g->cap_tiles);
     g->gbucket = c.take<uint2>(g->cap_buckets);
-    g->gpchunk = c.take<uint2>(g->cap_pchunks);
     g->gtilesum = c.take<uint32_t>(g->cap_tiles);
     // a workgroup-tier cell has more slots than the smallest group (64)
     g->cap_block = std::min<uint64_t>(n_cells, n_sd / 65 + 1);
@@ -256,7 +253,7 @@ sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
 {
     if (plan.grid.size() > g->cap_cells || plan.gchunk.size() > g->cap_chunks ||
         plan.gtile.size() > g->cap_tiles || plan.gbucket.size() > g->cap_buckets ||
-        plan.gpchunk.size() > g->cap_pchunks || plan.block.size() > g->cap_block) {
+        plan.block.size() > g->cap_block) {
         set_error("grid-tier tables exceed their capacity");
         return SDM_ENOMEM;
     }
@@ -268,8 +265,6 @@ sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
         SDM_HIP(hipMemcpyAsync(g->gtile, plan.gtile.data(), plan.gtile.size() * sizeof(uint2),
                                hipMemcpyHostToDevice, s));
         SDM_HIP(hipMemcpyAsync(g->gbucket, plan.gbucket.data(), plan.gbucket.size() * sizeof(uint2),
-                               hipMemcpyHostToDevice, s));
-        SDM_HIP(hipMemcpyAsync(g->gpchunk, plan.gpchunk.data(), plan.gpchunk.size() * sizeof(uint2),
                                hipMemcpyHostToDevice, s));
     }
     if (!plan.block.empty()) {
@@ -284,7 +279,6 @@ sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
     g->n_gchunk = static_cast<uint32_t>(plan.gchunk.size());
     g->n_gtile = static_cast<uint32_t>(plan.gtile.size());
     g->n_gbucket = static_cast<uint32_t>(plan.gbucket.size());
-    g->n_gpchunk = static_cast<uint32_t>(plan.gpchunk.size());
     return SDM_OK;
 }
 
@@ -298,8 +292,6 @@ void grid_args(const GridArrays& g, StepArgs* a)
     a->n_gtile = g.n_gtile;
     a->gbucket = g.gbucket;
     a->n_gbucket = g.n_gbucket;
-    a->gpchunk = g.gpchunk;
-    a->n_gpchunk = g.n_gpchunk;
     a->gtilesum = g.gtilesum;
     a->blist = g.blist;
     a->split_arrive = g.split_arrive;
@@ -366,10 +358,13 @@ static sdm_status launch_grid(hipStream_t s, const StepArgs& a)
     SDM_LAUNCHED();
     hipLaunchKernelGGL((k_grid_digits<BATCHED, true>), dim3(a.n_gchunk), blk, 0, s, a);
     SDM_LAUNCHED();
-    hipLaunchKernelGGL(k_grid_bucket_sort, dim3(a.n_gbucket), blk, 0, s, a);
+    hipLaunchKernelGGL((k_grid_bucket_pairs<BATCHED, PERM, PROBE>), dim3(a.n_gbucket), blk, 0, s, a);
     SDM_LAUNCHED();
-    hipLaunchKernelGGL((k_grid_pairs<BATCHED, PERM, PROBE>), dim3(a.n_gpchunk), blk, 0, s, a);
-    SDM_LAUNCHED();
+    if (!PERM) {
+        hipLaunchKernelGGL((k_grid_boundary<BATCHED, PROBE>),
+                           dim3((a.n_gbucket + kGridBlock - 1) / kGridBlock), blk, 0, s, a);
+        SDM_LAUNCHED();
+    }
     return SDM_OK;
 }
 

@@ -137,7 +137,7 @@ struct Plan {
     // workgroup tier: cells and their slot counts (ordered by plan_finish)
     std::vector<uint32_t> block, block_sizes;
     uint32_t block_big = 0;
-    std::vector<uint2> gchunk, gtile, gbucket, gpchunk;
+    std::vector<uint2> gchunk, gtile, gbucket;
 };
 
 // Device arrays of the grid tier (inside a workspace) and their capacities.
@@ -146,14 +146,13 @@ struct GridArrays {
     uint2* gchunk = nullptr;
     uint2* gtile = nullptr;
     uint2* gbucket = nullptr;
-    uint2* gpchunk = nullptr;
     uint32_t* gtilesum = nullptr;
     uint32_t* blist = nullptr;      // workgroup-tier cells
     uint32_t* split_arrive = nullptr;   // split tier: arrival counters of those cells
     uint32_t split_epoch = 0;       // split-tier steps since the counters were cleared
-    uint64_t cap_cells = 0, cap_chunks = 0, cap_tiles = 0, cap_buckets = 0, cap_pchunks = 0;
+    uint64_t cap_cells = 0, cap_chunks = 0, cap_tiles = 0, cap_buckets = 0;
     uint64_t cap_block = 0;
-    uint32_t n_grid = 0, n_gchunk = 0, n_gtile = 0, n_gbucket = 0, n_gpchunk = 0;
+    uint32_t n_grid = 0, n_gchunk = 0, n_gtile = 0, n_gbucket = 0;
     uint32_t n_block = 0, n_block_big = 0;
 };
 void carve_grid(Carver& c, uint64_t n_sd, uint32_t n_cells, GridArrays* g);

@@ -103,8 +103,6 @@ struct StepArgs {
     uint32_t n_gtile;
     const uint2* gbucket;         // (grid cell, digit) per digit bucket
     uint32_t n_gbucket;
-    const uint2* gpchunk;         // (grid cell, first pair) per pair chunk
-    uint32_t n_gpchunk;
     // workgroup tier: cells in descending order of storage slots; the first
     // n_block_big hold more than kBlockSmall slots
     const uint32_t* blist;
@@ -814,11 +812,15 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* s_red)
 //     each chunk writes its (key, slot) words there, so that every digit bucket
 //     (about 512 to 1024 entries) is contiguous and the buckets are in order;
 //   fine: one workgroup per bucket splits it by the next key bits into
-//     sub-buckets of one or two entries on average, in LDS, and ranks each
-//     entry within its sub-bucket.
-// The launches cover all grid cells at once: digit counts -> table tile sums
-// -> per-cell scan of the tile sums -> table tile scans -> placement -> bucket
-// sorts -> pair tests.  Same order and results as the other tiers.
+//     sub-buckets of one or two entries on average, in LDS, ranks each entry
+//     within its sub-bucket, and tests the pairs that lie inside the bucket
+//     (their multiplicities and radii gathered from the state by slot).
+// A pair that straddles two buckets (an odd first sorted position) is left to
+// a last launch, one thread per bucket, from the two slots the bucket
+// workgroups leave at those positions.  The launches cover all grid cells at
+// once: digit counts -> table tile sums -> per-cell scan of the tile sums ->
+// table tile scans -> placement -> bucket sorts with their pair tests ->
+// straddling pairs.  Same order and results as the other tiers.
 // ---------------------------------------------------------------------------
 constexpr int kGridBlock = 256;
 constexpr uint32_t kGridChunkLg = 11;     // smallest slot chunk, 2048 slots
@@ -829,9 +831,6 @@ constexpr uint32_t kGridMaxDigits = 1u << kGridMaxDigitBits;
 constexpr uint32_t kGridTile = 4096;      // table entries per tile
 constexpr uint32_t kGridSortCap = 2048;   // larger buckets are ordered through scr_tmp
 constexpr uint32_t kGridSubLg = 10;       // at most 2^10 sub-buckets per bucket
-// pairs per pair chunk: small, so that the chunks running at once on one XCD
-// cover few cells and their xi and r stay in that XCD's L2
-constexpr uint32_t kGridPairChunk = 512;
 // placement through LDS: chunks of kGridChunk slots with at most this many digits
 // (cells of up to 2^20 slots have at most 2^10)
 constexpr uint32_t kGridStagedDigits = 1024;
@@ -1006,150 +1005,229 @@ static __global__ __launch_bounds__(kGridBlock) void k_grid_tile_scan(const Step
     }
 }
 
-// Place the M entries of src into dst (LDS or the bucket's scr_tmp range) by
-// sub-bucket, then rank each within its sub-bucket and write its slot to pos.
-// On entry s_sub holds the exclusive starts of the sub-buckets; placement
-// advances each to its end, so sub-bucket b spans [end(b-1), end(b)).
-template <typename SubOf>
-__device__ __forceinline__ void grid_place_rank(const uint64_t* __restrict__ src, uint64_t* dst,
-                                                uint32_t M, uint32_t* s_sub, SubOf sub_of,
-                                                uint32_t* __restrict__ pos)
+struct GridFuseLds {
+    uint64_t kv[kGridSortCap];              // (key << 32 | slot) grouped by sub-bucket
+    uint32_t slot[kGridSortCap];            // storage slot at each sorted position
+    uint32_t sub[(1u << kGridSubLg) + 1];   // sub-bucket counts, then starts; [S] = M
+    uint32_t red[kGridBlock / kWave];
+    double dmax[kGridBlock / kWave];
+};
+
+// Pair test of the sorted positions (2m, 2m + 1) of a grid cell whose slots are
+// sa, sb: the state is read by slot (no pair of this step has changed them).
+template <bool PROBE>
+__device__ __forceinline__ bool grid_pair(const StepArgs& a, const CellJob& j, double scale,
+                                          uint32_t m, uint32_t sa, uint32_t sb, double& best)
 {
-    for (uint32_t i = threadIdx.x; i < M; i += kGridBlock) {
-        const uint64_t v = src[i];
-        dst[atomicAdd(&s_sub[sub_of(v)], 1u)] = v;
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < M; i += kGridBlock) {
-        const uint64_t v = dst[i];
-        const uint32_t b = sub_of(v);
-        const uint32_t e0 = b ? s_sub[b - 1] : 0u, e1 = s_sub[b];
-        uint32_t rank = 0;
-        for (uint32_t e = e0; e < e1; ++e) rank += dst[e] < v ? 1u : 0u;
-        pos[e0 + rank] = static_cast<uint32_t>(v);
+    const uint64_t xa = a.xi[j.off + sa], xb = a.xi[j.off + sb];
+    const double ra = a.r[j.off + sa], rb = a.r[j.off + sb];
+    if constexpr (PROBE) {
+        const double K = collection_kernel(j.kernel, j.kp, ra, rb);
+        best = fmax(best, collision_probability(xa >= xb ? xa : xb, K, j.dt, j.dV, scale));
+        return false;
+    } else {
+        const Words4 w = philox4x32_10(m >> 1, j.rng_cell, j.step, kTagUniform, j.k0, j.k1);
+        const double u = (m & 1u) ? uniform_open01(w.w[2], w.w[3]) : uniform_open01(w.w[0], w.w[1]);
+        return collide_pair_global(a, j, scale, u, sa, sb, xa, xb, ra, rb);
     }
 }
 
-// One workgroup per digit bucket: exact order of its (key, slot) words.
-static __global__ __launch_bounds__(kGridBlock) void k_grid_bucket_sort(const StepArgs a)
+// One workgroup per digit bucket: the exact order of its entries, then the
+// pair tests of the pairs with both members in it.  Up to kGridSortCap entries
+// are ordered in LDS; a larger bucket (cells of more than about 2^22 slots) is
+// ordered through its scr_tmp range and its order written to scr_pos.  The
+// bucket's first entry when its sorted position is odd, and its last when that
+// position is even and has a successor, leave their slot at their position in
+// scr_pos for k_grid_boundary.  Buckets of one cell are consecutive in the
+// list and go to one XCD, so that the gathers of a cell share its L2.
+template <bool BATCHED, bool PERM, bool PROBE = false>
+__global__ __launch_bounds__(kGridBlock) void k_grid_bucket_pairs(const StepArgs a)
 {
-    __shared__ uint32_t s_sub[1u << kGridSubLg];
-    __shared__ uint64_t s_kv[kGridSortCap];
-    __shared__ uint32_t s_red[kGridBlock / kWave];
-    const uint2 gb = a.gbucket[blockIdx.x];
+    constexpr int T = kGridBlock;
+    constexpr int K = kGridSortCap / T;
+    constexpr int W = T / kWave;
+    __shared__ GridFuseLds L;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const uint2 gb = a.gbucket[xcd_contiguous_block(blockIdx.x, gridDim.x)];
     const GridCell& gc = a.gcell[gb.x];
-    const uint32_t off = a.off_begin[gc.cell];
+    const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
+    const uint64_t off = j.off;
     const uint32_t lo = a.scr_cnt[off + gb.y * gc.ncol];
     const uint32_t M = a.scr_cnt[off + (gb.y + 1) * gc.ncol] - lo;   // entry nb is the sentinel
-    const uint64_t* src = a.scr_kv + off + lo;
-    uint32_t* pos = a.scr_pos + off + lo;
-    if (M < 2) {
-        if (M == 1 && threadIdx.x == 0) pos[0] = static_cast<uint32_t>(src[0]);
-        return;
+    const uint32_t n = gc.live;
+    if constexpr (PERM) {
+        if (gb.y == 0 && tid == 0) a.nlive_out[gc.cell] = n;
     }
+    if (M == 0) return;
     const uint32_t cb = gc.cb;
-    const uint32_t sb = min(ceil_log2(M) - 1u, kGridSubLg);
+    const uint32_t sb = M >= 2 ? min(ceil_log2(M) - 1u, kGridSubLg) : 0u;
     const uint32_t S = 1u << sb;
     const auto sub_of = [cb, sb](uint64_t v) {
         return bucket_of(static_cast<uint32_t>(v >> 32) << cb, sb);
     };
-    for (uint32_t b = threadIdx.x; b < S; b += kGridBlock) s_sub[b] = 0;
+    const bool in_lds = M <= kGridSortCap;
+    const uint64_t* src = a.scr_kv + off + lo;
+    uint32_t* pos_g = a.scr_pos + off;   // indexed by sorted position within the cell
+    for (uint32_t b = tid; b <= S; b += T) L.sub[b] = 0;
+
+    uint64_t kv[K];
+    uint32_t arr[K];
+    if (in_lds) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t i = tid + static_cast<uint32_t>(k) * T;
+            kv[k] = i < M ? src[i] : 0u;
+        }
+    }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < M; i += kGridBlock) atomicAdd(&s_sub[sub_of(src[i])], 1u);
+    if (in_lds) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t i = tid + static_cast<uint32_t>(k) * T;
+            arr[k] = i < M ? atomicAdd(&L.sub[sub_of(kv[k])], 1u) : 0u;
+        }
+    } else {
+        for (uint32_t i = tid; i < M; i += T) atomicAdd(&L.sub[sub_of(src[i])], 1u);
+    }
     __syncthreads();
-    // exclusive scan of s_sub[0, S): thread t owns a run of `per` entries
+    // exclusive scan of L.sub[0, S): thread t owns a run of `per` entries
     {
-        constexpr int W = kGridBlock / kWave;
-        const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-        const uint32_t per = (S + kGridBlock - 1) / kGridBlock;
-        const uint32_t b0 = threadIdx.x * per;
-        const uint32_t b1 = min(b0 + per, S);
+        const uint32_t per = (S + T - 1) / T;
+        const uint32_t b0 = min(tid * per, S), b1 = min(b0 + per, S);
         uint32_t run = 0;
-        for (uint32_t b = b0; b < b1; ++b) run += s_sub[b];
-        const uint32_t incl = wave_inclusive_sum(run, lane);
-        if (lane == kWave - 1) s_red[wv] = incl;
+        for (uint32_t b = b0; b < b1; ++b) run += L.sub[b];
+        const uint32_t incl = wave_inclusive_sum_dpp(run);
+        if (lane == kWave - 1) L.red[wv] = incl;
         __syncthreads();
         uint32_t before = incl - run;
 #pragma unroll
-        for (int w = 0; w < W; ++w) before += static_cast<uint32_t>(w) < wv ? s_red[w] : 0u;
+        for (int w = 0; w < W; ++w) before += static_cast<uint32_t>(w) < wv ? L.red[w] : 0u;
         for (uint32_t b = b0; b < b1; ++b) {
-            const uint32_t c = s_sub[b];
-            s_sub[b] = before;
+            const uint32_t c = L.sub[b];
+            L.sub[b] = before;
             before += c;
         }
+        if (tid == 0) L.sub[S] = M;
         __syncthreads();
     }
-    if (M <= kGridSortCap) grid_place_rank(src, s_kv, M, s_sub, sub_of, pos);
-    else grid_place_rank(src, a.scr_tmp + off + lo, M, s_sub, sub_of, pos);
-}
 
-// Pair tests: each thread takes the two pairs of one uniform call.  The pair
-// chunks of a cell go to one XCD (consecutive list entries, XCD-contiguous
-// block mapping), so the random reads of its xi and r share that XCD's L2.
-template <bool BATCHED, bool PERM, bool PROBE = false>
-__global__ __launch_bounds__(kGridBlock) void k_grid_pairs(const StepArgs a)
-{
-    __shared__ uint32_t s_red[kGridBlock / kWave];
-    __shared__ double s_max[kGridBlock / kWave];
-    const uint2 ch = a.gpchunk[xcd_contiguous_block(blockIdx.x, gridDim.x)];
-    const GridCell& gc = a.gcell[ch.x];
-    const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
-    const uint32_t n = gc.live;
-    if constexpr (PERM) {
-        // copy the sorted order of this chunk's pair range (both members) out
-        const uint32_t lo = 2 * ch.y;
-        const uint32_t hi = min(2 * (ch.y + kGridPairChunk), n);
-        for (uint32_t i = lo + threadIdx.x; i < hi; i += kGridBlock) a.perm_out[j.off + i] = a.scr_pos[j.off + i];
-        if (ch.y == 0 && threadIdx.x == 0) {
-            a.nlive_out[gc.cell] = n;
-            if (n & 1u) a.perm_out[j.off + n - 1] = a.scr_pos[j.off + n - 1];
+    if (in_lds) {
+        // scatter by sub-bucket start + arrival, then the rank in the sub-bucket
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (tid + static_cast<uint32_t>(k) * T < M) L.kv[L.sub[sub_of(kv[k])] + arr[k]] = kv[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (tid + static_cast<uint32_t>(k) * T >= M) continue;
+            const uint32_t b = sub_of(kv[k]);
+            const uint32_t e0 = L.sub[b], e1 = L.sub[b + 1];
+            uint32_t rank = 0;
+            for (uint32_t e = e0; e < e1; ++e) rank += L.kv[e] < kv[k] ? 1u : 0u;
+            const uint32_t p = e0 + rank;
+            const uint32_t slot = static_cast<uint32_t>(kv[k]);
+            if constexpr (PERM) {
+                a.perm_out[off + lo + p] = slot;
+            } else {
+                L.slot[p] = slot;
+                const uint32_t P = lo + p;
+                if ((p == 0 && (P & 1u)) || (p == M - 1 && !(P & 1u) && P + 1 < n)) pos_g[P] = slot;
+            }
         }
-        return;
+        if constexpr (PERM) return;
+    } else {
+        // through global memory: place by sub-bucket into scr_tmp, rank, and
+        // write the slot of every sorted position to scr_pos
+        uint64_t* dst = a.scr_tmp + off + lo;
+        for (uint32_t i = tid; i < M; i += T) {
+            const uint64_t v = src[i];
+            dst[atomicAdd(&L.sub[sub_of(v)], 1u)] = v;
+        }
+        __syncthreads();   // L.sub[b] now ends sub-bucket b
+        for (uint32_t i = tid; i < M; i += T) {
+            const uint64_t v = dst[i];
+            const uint32_t b = sub_of(v);
+            const uint32_t e0 = b ? L.sub[b - 1] : 0u, e1 = L.sub[b];
+            uint32_t rank = 0;
+            for (uint32_t e = e0; e < e1; ++e) rank += dst[e] < v ? 1u : 0u;
+            pos_g[lo + e0 + rank] = static_cast<uint32_t>(v);
+        }
+        __syncthreads();
+        if constexpr (PERM) {
+            for (uint32_t i = tid; i < M; i += T) a.perm_out[off + lo + i] = pos_g[lo + i];
+            return;
+        }
     }
-    const uint32_t npairs = n >> 1;
-    const double scale = npairs ? upscale_factor(n) : 0.0;
+    __syncthreads();
+
+    // pairs (2m, 2m + 1) with both members in the bucket: m in [m_a, m_b)
+    const uint32_t m_a = (lo + 1u) >> 1, m_b = (lo + M) >> 1;
+    const double scale = n >= 2 ? upscale_factor(n) : 0.0;
+    uint32_t coll = 0;
+    double best = 0.0;
+    for (uint32_t m = m_a + tid; m < m_b; m += T) {
+        const uint32_t sa = in_lds ? L.slot[2 * m - lo] : pos_g[2 * m];
+        const uint32_t sb2 = in_lds ? L.slot[2 * m + 1 - lo] : pos_g[2 * m + 1];
+        if (grid_pair<PROBE>(a, j, scale, m, sa, sb2, best)) ++coll;
+    }
     if constexpr (PROBE) {
-        // largest P_ij of the chunk's pairs, then one atomic max per workgroup
-        double best = 0.0;
-        const uint32_t m_end = min(ch.y + kGridPairChunk, npairs);
-        for (uint32_t m = ch.y + threadIdx.x; m < m_end; m += kGridBlock) {
-            const uint32_t sa = a.scr_pos[j.off + 2 * m], sb = a.scr_pos[j.off + 2 * m + 1];
-            const uint64_t xa = a.xi[j.off + sa], xb = a.xi[j.off + sb];
-            const double K = collection_kernel(j.kernel, j.kp, a.r[j.off + sa], a.r[j.off + sb]);
-            best = fmax(best, collision_probability(xa >= xb ? xa : xb, K, j.dt, j.dV, scale));
-        }
 #pragma unroll
         for (int d = kWave / 2; d >= 1; d >>= 1) best = fmax(best, __shfl_xor(best, d, kWave));
-        if ((threadIdx.x & (kWave - 1)) == 0) s_max[threadIdx.x / kWave] = best;
+        if (lane == 0) L.dmax[wv] = best;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double b = s_max[0];
-            for (int w = 1; w < kGridBlock / kWave; ++w) b = fmax(b, s_max[w]);
+        if (tid == 0) {
+            double b = L.dmax[0];
+            for (int w = 1; w < W; ++w) b = fmax(b, L.dmax[w]);
             if (b > 0.0)
                 atomicMax(reinterpret_cast<unsigned long long*>(a.cell_max + gc.cell),
                           static_cast<unsigned long long>(__double_as_longlong(b)));
         }
         return;
     }
-    uint32_t coll = 0;
-    const uint32_t h_end = (min(ch.y + kGridPairChunk, npairs) + 1u) / 2u;
-    for (uint32_t h = ch.y / 2u + threadIdx.x; h < h_end; h += kGridBlock) {
-        const Words4 w = philox4x32_10(h, j.rng_cell, j.step, kTagUniform, j.k0, j.k1);
-#pragma unroll
-        for (uint32_t t = 0; t < 2; ++t) {
-            const uint32_t m = 2 * h + t;
-            if (m >= npairs) break;
-            const double u = t ? uniform_open01(w.w[2], w.w[3]) : uniform_open01(w.w[0], w.w[1]);
-            const uint32_t sa = a.scr_pos[j.off + 2 * m], sb = a.scr_pos[j.off + 2 * m + 1];
-            const uint64_t xa = a.xi[j.off + sa], xb = a.xi[j.off + sb];
-            const double ra = a.r[j.off + sa], rb = a.r[j.off + sb];
-            if (collide_pair_global(a, j, scale, u, sa, sb, xa, xb, ra, rb)) ++coll;
-        }
-    }
-    const uint32_t tot = block_sum<kGridBlock>(coll, s_red);
-    if (threadIdx.x == 0 && tot) {
+    const uint32_t tot = block_sum<T>(coll, L.red);
+    if (tid == 0 && tot) {
         if constexpr (BATCHED) atomicAdd(&a.inst[j.inst].collisions, static_cast<unsigned long long>(tot));
         else atomicAdd(a.stats + (blockIdx.x % kStatSlots) * kStatStride + 1, static_cast<unsigned long long>(tot));
+    }
+}
+
+// The pairs that straddle two digit buckets: one thread per bucket whose first
+// sorted position lo is odd tests the pair (lo - 1, lo) from the slots the
+// bucket workgroups left in scr_pos.
+template <bool BATCHED, bool PROBE = false>
+__global__ __launch_bounds__(kGridBlock) void k_grid_boundary(const StepArgs a)
+{
+    __shared__ uint32_t s_red[kGridBlock / kWave];
+    const uint32_t i = blockIdx.x * kGridBlock + threadIdx.x;
+    uint32_t coll = 0;
+    if (i < a.n_gbucket) {
+        const uint2 gb = a.gbucket[i];
+        const GridCell& gc = a.gcell[gb.x];
+        const uint64_t off = a.off_begin[gc.cell];
+        const uint32_t lo = a.scr_cnt[off + gb.y * gc.ncol];
+        const uint32_t hi = a.scr_cnt[off + (gb.y + 1) * gc.ncol];
+        if (hi > lo && (lo & 1u)) {
+            const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
+            const double scale = upscale_factor(gc.live);
+            const uint32_t sa = a.scr_pos[off + lo - 1], sb = a.scr_pos[off + lo];
+            double best = 0.0;
+            if (grid_pair<PROBE>(a, j, scale, (lo - 1u) >> 1, sa, sb, best)) {
+                if constexpr (BATCHED) atomicAdd(&a.inst[j.inst].collisions, 1ull);
+                else ++coll;
+            }
+            if constexpr (PROBE) {
+                if (best > 0.0)
+                    atomicMax(reinterpret_cast<unsigned long long*>(a.cell_max + gc.cell),
+                              static_cast<unsigned long long>(__double_as_longlong(best)));
+            }
+        }
+    }
+    if constexpr (!BATCHED && !PROBE) {
+        const uint32_t tot = block_sum<kGridBlock>(coll, s_red);
+        if (threadIdx.x == 0 && tot)
+            atomicAdd(a.stats + (blockIdx.x % kStatSlots) * kStatStride + 1, static_cast<unsigned long long>(tot));
     }
 }
 
