@@ -127,7 +127,7 @@ struct LaunchShape {
 };
 
 // Work lists of one step: wave-tier groups of consecutive cells and the
-// grid-tier cells with their chunk, table-tile, bucket and pair-chunk lists.
+// grid-tier cells with their chunk, table-tile and bucket lists.
 struct Plan {
     std::vector<uint32_t> group_begin, group_end;
     uint32_t wave_cells = 0;
