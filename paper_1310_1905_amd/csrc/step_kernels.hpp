@@ -1006,8 +1006,10 @@ static __global__ __launch_bounds__(kGridBlock) void k_grid_tile_scan(const Step
 }
 
 struct GridFuseLds {
-    uint64_t kv[kGridSortCap];              // (key << 32 | slot) grouped by sub-bucket
-    uint32_t slot[kGridSortCap];            // storage slot at each sorted position
+    union {                                 // (a smaller footprint: more workgroups per CU)
+        uint64_t kv[kGridSortCap];          // (key << 32 | slot) grouped by sub-bucket
+        uint32_t slot[kGridSortCap];        // then the storage slot at each sorted position
+    };
     uint32_t sub[(1u << kGridSubLg) + 1];   // sub-bucket counts, then starts; [S] = M
     uint32_t red[kGridBlock / kWave];
     double dmax[kGridBlock / kWave];
@@ -1119,14 +1121,22 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_bucket_pairs(const StepArgs
         for (int k = 0; k < K; ++k)
             if (tid + static_cast<uint32_t>(k) * T < M) L.kv[L.sub[sub_of(kv[k])] + arr[k]] = kv[k];
         __syncthreads();
+        uint32_t pk[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
+            pk[k] = 0;
             if (tid + static_cast<uint32_t>(k) * T >= M) continue;
             const uint32_t b = sub_of(kv[k]);
             const uint32_t e0 = L.sub[b], e1 = L.sub[b + 1];
             uint32_t rank = 0;
             for (uint32_t e = e0; e < e1; ++e) rank += L.kv[e] < kv[k] ? 1u : 0u;
-            const uint32_t p = e0 + rank;
+            pk[k] = e0 + rank;
+        }
+        __syncthreads();   // the slots overwrite the sort array
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (tid + static_cast<uint32_t>(k) * T >= M) continue;
+            const uint32_t p = pk[k];
             const uint32_t slot = static_cast<uint32_t>(kv[k]);
             if constexpr (PERM) {
                 a.perm_out[off + lo + p] = slot;
