@@ -165,6 +165,7 @@ struct sdm_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     LaunchShape shape;
+    StreamFork fork;   // side stream of the small-instance tiers
 };
 
 static sdm_status rebuild_lists(sdm_batch* b)
@@ -209,11 +210,22 @@ static sdm_status enqueue_step(sdm_batch* b)
     a.scr_cnt = b->L.scr_cnt;
     grid_args(b->L.grid, &a);
     SDM_TRY(launch_step(b->stream, a, b->L.group_begin, b->L.group_end, b->n_groups, b->shape,
-                        true, false));
+                        true, false, false, nullptr, &b->fork));
     hipLaunchKernelGGL(k_advance_instances, dim3(grid_for(b->max_inst, 256, 1024)), dim3(256), 0,
                        b->stream, b->L.inst, b->max_inst);
     SDM_LAUNCHED();
     return SDM_OK;
+}
+
+static void destroy_fork(StreamFork& f)
+{
+    if (f.begin) hipEventDestroy(f.begin);
+    if (f.end) hipEventDestroy(f.end);
+    if (f.side) {
+        hipStreamSynchronize(f.side);
+        hipStreamDestroy(f.side);
+    }
+    f = StreamFork{};
 }
 
 static void drop_graph(sdm_batch* b)
@@ -257,7 +269,16 @@ extern "C" sdm_status sdm_batch_create(sdm_batch** out, void* stream, void* work
                        reinterpret_cast<unsigned long long*>(L.inst), words, 0ull);
     SDM_LAUNCHED();
     SDM_HIP(hipStreamSynchronize(s));
+    StreamFork fork;
+    if (hipStreamCreateWithFlags(&fork.side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&fork.begin, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&fork.end, hipEventDisableTiming) != hipSuccess) {
+        set_error("side stream or events of the batch: %s", hipGetErrorString(hipGetLastError()));
+        destroy_fork(fork);
+        return SDM_EDEVICE;
+    }
     auto* b = new sdm_batch();
+    b->fork = fork;
     b->stream = s;
     b->max_sd = max_sd;
     b->max_cells = max_cells;
@@ -618,5 +639,6 @@ extern "C" void sdm_batch_destroy(sdm_batch* b)
 {
     if (!b) return;
     drop_graph(b);
+    destroy_fork(b->fork);
     delete b;
 }

@@ -425,7 +425,8 @@ static sdm_status launch_wave_probe(hipStream_t s, const StepArgs& a, uint32_t n
 
 sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* group_begin,
                        const uint32_t* group_end, uint32_t n_groups, const LaunchShape& shape,
-                       bool batched, bool perm, bool probe, bool* split_enqueued)
+                       bool batched, bool perm, bool probe, bool* split_enqueued,
+                       const StreamFork* fork)
 {
     if (probe) {
         if (batched || perm) {
@@ -445,6 +446,17 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
         if (base.n_grid > 0) SDM_TRY((launch_grid<false, false, true>(s, base)));
         return SDM_OK;
     }
+    const bool forked = fork && fork->side && fork->begin && fork->end && base.n_grid > 0 &&
+                        (n_groups > 0 || base.n_block > 0);
+    hipStream_t s_small = s;
+    if (forked) {
+        SDM_HIP(hipEventRecord(fork->begin, s));
+        SDM_HIP(hipStreamWaitEvent(fork->side, fork->begin, 0));
+        s_small = fork->side;
+    }
+    // the wavefront and workgroup tiers (on the side stream when forked; it is
+    // joined back even when one of these launches fails)
+    sdm_status st = SDM_OK;
     if (n_groups > 0) {
         StepArgs a = base;
         a.group_begin = group_begin;
@@ -452,25 +464,30 @@ sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* grou
         a.n_groups = n_groups;
         a.groups_per_wave = shape.groups_per_wave;
         a.xcd_remap = shape.xcd_remap;
-        if (batched) SDM_TRY(perm ? launch_wave_any<true, true>(s, a, n_groups, shape)
-                                  : launch_wave_any<true, false>(s, a, n_groups, shape));
-        else SDM_TRY(perm ? launch_wave_any<false, true>(s, a, n_groups, shape)
-                          : launch_wave_any<false, false>(s, a, n_groups, shape));
+        if (batched) st = perm ? launch_wave_any<true, true>(s_small, a, n_groups, shape)
+                               : launch_wave_any<true, false>(s_small, a, n_groups, shape);
+        else st = perm ? launch_wave_any<false, true>(s_small, a, n_groups, shape)
+                       : launch_wave_any<false, false>(s_small, a, n_groups, shape);
     }
-    if (base.n_block > 0) {
+    if (st == SDM_OK && base.n_block > 0) {
         if (batched)
-            SDM_TRY(perm ? (launch_block<true, true, false>(s, base, 0, nullptr)) : (launch_block<true, false, false>(s, base, 0, nullptr)));
+            st = perm ? launch_block<true, true, false>(s_small, base, 0, nullptr)
+                      : launch_block<true, false, false>(s_small, base, 0, nullptr);
         else
-            SDM_TRY(perm ? (launch_block<false, true, false>(s, base, shape.block_split, split_enqueued))
-                         : (launch_block<false, false, false>(s, base, shape.block_split, split_enqueued)));
+            st = perm ? launch_block<false, true, false>(s_small, base, shape.block_split, split_enqueued)
+                      : launch_block<false, false, false>(s_small, base, shape.block_split, split_enqueued);
     }
-    if (base.n_grid > 0) {
+    if (forked) SDM_HIP(hipEventRecord(fork->end, fork->side));
+    // the grid tier on s, then s waits for the side stream
+    sdm_status gst = SDM_OK;
+    if (st == SDM_OK && base.n_grid > 0) {
         if (batched)
-            SDM_TRY(perm ? (launch_grid<true, true, false>(s, base)) : (launch_grid<true, false, false>(s, base)));
+            gst = perm ? launch_grid<true, true, false>(s, base) : launch_grid<true, false, false>(s, base);
         else
-            SDM_TRY(perm ? (launch_grid<false, true, false>(s, base)) : (launch_grid<false, false, false>(s, base)));
+            gst = perm ? launch_grid<false, true, false>(s, base) : launch_grid<false, false, false>(s, base);
     }
-    return SDM_OK;
+    if (forked) SDM_HIP(hipStreamWaitEvent(s, fork->end, 0));
+    return st != SDM_OK ? st : gst;
 }
 
 void carve_device_plan(Carver& c, uint32_t nc, DevicePlanArrays* p)

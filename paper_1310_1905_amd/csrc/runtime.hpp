@@ -175,10 +175,19 @@ void plan_finish(Plan& plan);
 // probe: instead of the collisions, the largest P_ij of every cell goes to
 // base.cell_max (single runs only; grid-tier entries must start at 0).
 // *split_enqueued (nullable) becomes true once a split-tier kernel is enqueued.
+// fork (nullable): a side stream and two events; when the grid tier and another
+// tier both have cells, the wavefront and workgroup tiers run on the side stream,
+// concurrently with the grid tier's chain of launches, and s waits for them
+// before this returns (their cells are disjoint, and the counters they share
+// are integer atomics, so the results do not depend on the interleaving).
+struct StreamFork {
+    hipStream_t side = nullptr;
+    hipEvent_t begin = nullptr, end = nullptr;
+};
 sdm_status launch_step(hipStream_t s, const StepArgs& base, const uint32_t* group_begin,
                        const uint32_t* group_end, uint32_t n_groups, const LaunchShape& shape,
                        bool batched, bool perm, bool probe = false,
-                       bool* split_enqueued = nullptr);
+                       bool* split_enqueued = nullptr, const StreamFork* fork = nullptr);
 
 bool shape_valid(const LaunchShape& sh);
 
