@@ -211,8 +211,8 @@ void plan_finish(Plan& plan)
         for (uint32_t t = 0; t < gc.ntiles; ++t) plan.gtile.push_back(make_uint2(i, t * kGridTile));
         tile += gc.ntiles;
         for (uint64_t s0 = 0; s0 < n; s0 += 1u << gc.lgc)
-            plan.gchunk.push_back(make_uint2(i, static_cast<uint32_t>(s0)));
-        for (uint32_t d = 0; d < (1u << gc.cb); ++d) plan.gbucket.push_back(make_uint2(i, d));
+            plan.gchunk.push_back(make_uint4(i, static_cast<uint32_t>(s0), gc.cell, 0u));
+        for (uint32_t d = 0; d < (1u << gc.cb); ++d) plan.gbucket.push_back(make_uint4(i, d, gc.cell, 0u));
     }
 }
 
@@ -239,9 +239,9 @@ void carve_grid(Carver& c, uint64_t n_sd, uint32_t n_cells, GridArrays* g)
     // 2^cb <= 2^(ceil(log2 N) - 10) < N / 512
     g->cap_buckets = n_sd / (1u << (kGridBucketLg - 1)) + g->cap_cells;
     g->gcell = c.take<GridCell>(g->cap_cells);
-    g->gchunk = c.take<uint2>(g->cap_chunks);
+    g->gchunk = c.take<uint4>(g->cap_chunks);
     g->gtile = c.take<uint2>(g->cap_tiles);
-    g->gbucket = c.take<uint2>(g->cap_buckets);
+    g->gbucket = c.take<uint4>(g->cap_buckets);
     g->gtilesum = c.take<uint32_t>(g->cap_tiles);
     // a workgroup-tier cell has more slots than the smallest group (64)
     g->cap_block = std::min<uint64_t>(n_cells, n_sd / 65 + 1);
@@ -260,11 +260,11 @@ sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
     if (!plan.grid.empty()) {
         SDM_HIP(hipMemcpyAsync(g->gcell, plan.grid.data(), plan.grid.size() * sizeof(GridCell),
                                hipMemcpyHostToDevice, s));
-        SDM_HIP(hipMemcpyAsync(g->gchunk, plan.gchunk.data(), plan.gchunk.size() * sizeof(uint2),
+        SDM_HIP(hipMemcpyAsync(g->gchunk, plan.gchunk.data(), plan.gchunk.size() * sizeof(uint4),
                                hipMemcpyHostToDevice, s));
         SDM_HIP(hipMemcpyAsync(g->gtile, plan.gtile.data(), plan.gtile.size() * sizeof(uint2),
                                hipMemcpyHostToDevice, s));
-        SDM_HIP(hipMemcpyAsync(g->gbucket, plan.gbucket.data(), plan.gbucket.size() * sizeof(uint2),
+        SDM_HIP(hipMemcpyAsync(g->gbucket, plan.gbucket.data(), plan.gbucket.size() * sizeof(uint4),
                                hipMemcpyHostToDevice, s));
     }
     if (!plan.block.empty()) {

@@ -137,15 +137,16 @@ struct Plan {
     // workgroup tier: cells and their slot counts (ordered by plan_finish)
     std::vector<uint32_t> block, block_sizes;
     uint32_t block_big = 0;
-    std::vector<uint2> gchunk, gtile, gbucket;
+    std::vector<uint2> gtile;
+    std::vector<uint4> gchunk, gbucket;
 };
 
 // Device arrays of the grid tier (inside a workspace) and their capacities.
 struct GridArrays {
     GridCell* gcell = nullptr;
-    uint2* gchunk = nullptr;
+    uint4* gchunk = nullptr;
     uint2* gtile = nullptr;
-    uint2* gbucket = nullptr;
+    uint4* gbucket = nullptr;
     uint32_t* gtilesum = nullptr;
     uint32_t* blist = nullptr;      // workgroup-tier cells
     uint32_t* split_arrive = nullptr;   // split tier: arrival counters of those cells

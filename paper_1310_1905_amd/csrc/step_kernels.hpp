@@ -97,11 +97,13 @@ struct StepArgs {
     // grid tier (cells spread over many workgroups)
     struct GridCell* gcell;
     uint32_t n_grid;
-    const uint2* gchunk;          // (grid cell, first slot) per slot chunk
+    // (grid cell, first slot, cell) per slot chunk: the cell is there so that its
+    // offset and job load beside the grid cell instead of after it
+    const uint4* gchunk;
     uint32_t n_gchunk;
     const uint2* gtile;           // (grid cell, first entry) per count-table tile
     uint32_t n_gtile;
-    const uint2* gbucket;         // (grid cell, digit) per digit bucket
+    const uint4* gbucket;         // (grid cell, digit, cell) per digit bucket
     uint32_t n_gbucket;
     // workgroup tier: cells in descending order of storage slots; the first
     // n_block_big hold more than kBlockSmall slots
@@ -843,6 +845,12 @@ constexpr uint32_t kGridStagedDigits = 1024;
 // consecutive threads write consecutive words of a run instead of each word
 // being a memory request of its own.  Larger chunks place every word straight
 // at its digit's cursor.
+// The slots go in rounds of kGridQuads quads of four per thread (one round for
+// a chunk of kGridChunk slots).  The first round's multiplicities are requested
+// as soon as the cell's offset is known; its keys are drawn and the LDS
+// counters set up while they are in flight.
+constexpr uint32_t kGridQuads = kGridChunk / (4 * kGridBlock);
+
 template <bool BATCHED, bool PLACE>
 __global__ __launch_bounds__(kGridBlock) void k_grid_digits(const StepArgs a)
 {
@@ -850,12 +858,44 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_digits(const StepArgs a)
     // local cursors and the kGridChunk staged words, over the same bytes
     constexpr uint32_t kRawWords = PLACE ? kGridStagedDigits + kGridChunk : kGridMaxDigits / 2;
     static_assert(!PLACE || kRawWords >= kGridMaxDigits / 2, "direct counters fit the buffer");
+    static_assert(kGridQuads * 4 * kGridBlock == kGridChunk, "one round per smallest chunk");
     __shared__ uint64_t s_raw[kRawWords];
     __shared__ uint32_t s_red[kGridBlock / kWave];
-    const uint2 ch = a.gchunk[blockIdx.x];
+    const uint4 ch = a.gchunk[blockIdx.x];
+    const uint32_t off = a.off_begin[ch.z];
+    const uint32_t n_slots = a.off_end[ch.z] - off;
     const GridCell& gc = a.gcell[ch.x];
-    const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
+    const uint32_t s_end = min(ch.y + (1u << gc.lgc), n_slots);
+    const uint32_t q_end = (s_end + 3u) / 4u;
+    const uint32_t q_first = ch.y / 4u + threadIdx.x;
+    const uint64_t* xi = a.xi + off;
+    uint64_t xv[kGridQuads][4];
+    const auto load_round = [&](uint32_t q0) {
+#pragma unroll
+        for (uint32_t i = 0; i < kGridQuads; ++i) {
+            const uint32_t q = q0 + i * kGridBlock;
+#pragma unroll
+            for (uint32_t t = 0; t < 4; ++t) {
+                // branch-free: every load in flight together (the index is
+                // clamped to the chunk's last slot; s_end > ch.y)
+                const uint32_t sl = 4 * q + t;
+                const uint64_t v = xi[sl < s_end ? sl : s_end - 1u];
+                xv[i][t] = sl < s_end ? v : 0u;
+            }
+        }
+    };
+    load_round(q_first);
+
+    const CellJob j = resolve_cell<BATCHED>(a, ch.z);
     const uint32_t cb = gc.cb, D = 1u << cb, ncol = gc.ncol, col = ch.y >> gc.lgc;
+    Words4 kw[kGridQuads];
+    const auto draw_round = [&](uint32_t q0) {
+#pragma unroll
+        for (uint32_t i = 0; i < kGridQuads; ++i)
+            kw[i] = philox4x32_10(q0 + i * kGridBlock, j.rng_cell, j.step, kTagShuffle, j.k0, j.k1);
+    };
+    draw_round(q_first);
+
     uint32_t* tbl = a.scr_cnt + j.off;
     // uniform over the workgroup
     const bool staged = PLACE && gc.lgc == kGridChunkLg && D <= kGridStagedDigits;
@@ -901,28 +941,29 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_digits(const StepArgs a)
         for (uint32_t d = threadIdx.x; d < D; d += kGridBlock) s_cnt[d] = PLACE ? tbl[d * ncol + col] : 0u;
     }
     __syncthreads();
-    const uint32_t s_end = min(ch.y + (1u << gc.lgc), j.n_slots);
-    const uint32_t q_end = (s_end + 3u) / 4u;
-    const uint64_t* xi = a.xi + j.off;
-    for (uint32_t q = ch.y / 4u + threadIdx.x; q < q_end; q += kGridBlock) {
-        bool live[4];
+    for (uint32_t q0 = q_first; q0 < q_end; q0 += kGridQuads * kGridBlock) {
+        if (q0 != q_first) {
+            load_round(q0);
+            draw_round(q0);
+        }
 #pragma unroll
-        for (uint32_t t = 0; t < 4; ++t) live[t] = 4 * q + t < s_end && xi[4 * q + t] != 0;
-        const Words4 w = philox4x32_10(q, j.rng_cell, j.step, kTagShuffle, j.k0, j.k1);
+        for (uint32_t i = 0; i < kGridQuads; ++i) {
+            const uint32_t q = q0 + i * kGridBlock;
 #pragma unroll
-        for (uint32_t t = 0; t < 4; ++t) {
-            if (!live[t]) continue;
-            const uint32_t d = bucket_of(w.w[t], cb);
-            if constexpr (PLACE) {
-                const uint64_t word = (static_cast<uint64_t>(w.w[t]) << 32) | (4 * q + t);
-                if (staged) {
-                    s_stage[atomicAdd(&s_loc[d], 1u)] = word;   // < m_chunk <= kGridChunk
+            for (uint32_t t = 0; t < 4; ++t) {
+                if (xv[i][t] == 0u) continue;   // dead, or past the chunk (read as 0)
+                const uint32_t d = bucket_of(kw[i].w[t], cb);
+                if constexpr (PLACE) {
+                    const uint64_t word = (static_cast<uint64_t>(kw[i].w[t]) << 32) | (4 * q + t);
+                    if (staged) {
+                        s_stage[atomicAdd(&s_loc[d], 1u)] = word;   // < m_chunk <= kGridChunk
+                    } else {
+                        const uint32_t p = atomicAdd(&s_cnt[d], 1u);
+                        a.scr_kv[j.off + p] = word;
+                    }
                 } else {
-                    const uint32_t p = atomicAdd(&s_cnt[d], 1u);
-                    a.scr_kv[j.off + p] = word;
+                    atomicAdd(&s_cnt[d], 1u);
                 }
-            } else {
-                atomicAdd(&s_cnt[d], 1u);
             }
         }
     }
@@ -1052,9 +1093,9 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_bucket_pairs(const StepArgs
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid / kWave);
-    const uint2 gb = a.gbucket[xcd_contiguous_block(blockIdx.x, gridDim.x)];
+    const uint4 gb = a.gbucket[xcd_contiguous_block(blockIdx.x, gridDim.x)];
     const GridCell& gc = a.gcell[gb.x];
-    const CellJob j = resolve_cell<BATCHED>(a, gc.cell);
+    const CellJob j = resolve_cell<BATCHED>(a, gb.z);
     const uint64_t off = j.off;
     const uint32_t lo = a.scr_cnt[off + gb.y * gc.ncol];
     const uint32_t M = a.scr_cnt[off + (gb.y + 1) * gc.ncol] - lo;   // entry nb is the sentinel
@@ -1213,9 +1254,9 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_boundary(const StepArgs a)
     const uint32_t i = blockIdx.x * kGridBlock + threadIdx.x;
     uint32_t coll = 0;
     if (i < a.n_gbucket) {
-        const uint2 gb = a.gbucket[i];
+        const uint4 gb = a.gbucket[i];
         const GridCell& gc = a.gcell[gb.x];
-        const uint64_t off = a.off_begin[gc.cell];
+        const uint64_t off = a.off_begin[gb.z];
         const uint32_t lo = a.scr_cnt[off + gb.y * gc.ncol];
         const uint32_t hi = a.scr_cnt[off + (gb.y + 1) * gc.ncol];
         if (hi > lo && (lo & 1u)) {
@@ -1534,9 +1575,15 @@ __global__ __launch_bounds__(T) void k_split_cells(const StepArgs a, const uint3
         for (int t = 0; t < 4; ++t) {
             const int k = 4 * i + t;
             const uint32_t s = 4 * q + static_cast<uint32_t>(t);
-            xv[k] = s < n ? a.xi[j.off + s] : 0u;
+            // branch-free: the index is clamped to the cell's last slot
+            const uint32_t sc = s < n ? s : n - 1u;
+            const uint64_t xq = a.xi[j.off + sc];
+            xv[k] = s < n ? xq : 0u;
             rv[k] = 0.0;
-            if constexpr (!PERM) rv[k] = s < n ? a.r[j.off + s] : 0.0;
+            if constexpr (!PERM) {
+                const double rq = a.r[j.off + sc];
+                rv[k] = s < n ? rq : 0.0;
+            }
             key[k] = w.w[t];
             const uint32_t d = bucket_of(key[k], lgG);
             const bool live = xv[k] != 0u;
