@@ -1218,11 +1218,17 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_bucket_pairs(const StepArgs
     const double scale = n >= 2 ? upscale_factor(n) : 0.0;
     uint32_t coll = 0;
     double best = 0.0;
-    for (uint32_t m = m_a + tid; m < m_b; m += T) {
-        const uint32_t sa = in_lds ? L.slot[2 * m - lo] : pos_g[2 * m];
-        const uint32_t sb2 = in_lds ? L.slot[2 * m + 1 - lo] : pos_g[2 * m + 1];
-        if (grid_pair<PROBE>(a, j, scale, m, sa, sb2, best)) ++coll;
-    }
+    // slots[p - first] is the slot at sorted position p of the cell; the branch
+    // on in_lds is uniform, so that the LDS case reads the slots as LDS (a
+    // pointer that may be either is a flat access, whose wait also covers the
+    // stores)
+    const auto run_pairs = [&](const uint32_t* slots, uint32_t first) {
+        for (uint32_t m = m_a + tid; m < m_b; m += T)
+            if (grid_pair<PROBE>(a, j, scale, m, slots[2 * m - first], slots[2 * m + 1 - first], best))
+                ++coll;
+    };
+    if (in_lds) run_pairs(L.slot, lo);
+    else run_pairs(pos_g, 0u);
     if constexpr (PROBE) {
 #pragma unroll
         for (int d = kWave / 2; d >= 1; d >>= 1) best = fmax(best, __shfl_xor(best, d, kWave));
