@@ -101,10 +101,13 @@ __global__ __launch_bounds__(kDiagBlock) void k_sd_conc(const uint32_t* __restri
         uint32_t cnt = 0;
         for (uint32_t base = 0; base < n; base += 4u * 64u) {
             uint64_t xv[4];
+            // branch-free loads (the index clamped to the cell's last slot, n > 0
+            // here), so that all four are in flight together
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const uint32_t i = base + lane + 64u * t;
-                xv[t] = i < n ? xi[b + i] : 0u;
+                const uint64_t v = xi[b + (i < n ? i : n - 1u)];
+                xv[t] = i < n ? v : 0u;
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) cnt += static_cast<uint32_t>(__popcll(__ballot(xv[t] != 0)));

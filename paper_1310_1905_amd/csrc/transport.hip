@@ -147,28 +147,43 @@ struct Flow {
     KernelParams kp;
 };
 
-// New position of the particle at (x0, z0) with radius r: advection from the
-// Courant numbers of its time-level-n cell, then the fall, the periodic wrap in
-// x, and a clamp into the boundary row for a particle that left through the
-// bottom or the top (*left).  *cell_old is that time-level-n cell.
-__device__ __forceinline__ void move_particle(const Flow& f, double x0, double z0, double r,
-                                              double& xn, double& zn, bool& left,
-                                              uint32_t& cell_old)
+// The Courant numbers a particle's advection reads: those of the left and
+// right x edges and of the bottom and top z edges of its time-level-n cell
+// (column i, row k).  Requested apart from their use, so that a thread can
+// have those of all its particles in flight together.
+struct EdgeCourant {
+    uint32_t i, k;
+    double l, rr, b, tp;
+};
+__device__ __forceinline__ EdgeCourant load_courant(const Flow& f, double x0, double z0)
 {
-    const uint32_t i = column_of(x0, f.dx, f.nx);
-    const uint32_t k = column_of(z0, f.dz, f.nz);
-    xn = x0;
-    zn = z0;
+    EdgeCourant e;
+    e.i = column_of(x0, f.dx, f.nx);
+    e.k = column_of(z0, f.dz, f.nz);
+    e.l = e.rr = e.b = e.tp = 0.0;
     if (f.cx) {
-        const double l = f.cx[static_cast<uint64_t>(k) * f.nx + i];
-        const double rr = f.cx[static_cast<uint64_t>(k) * f.nx + (i + 1u == f.nx ? 0u : i + 1u)];
-        xn = advect_1d(x0, f.dx, i, l, rr);
+        e.l = f.cx[static_cast<uint64_t>(e.k) * f.nx + e.i];
+        e.rr = f.cx[static_cast<uint64_t>(e.k) * f.nx + (e.i + 1u == f.nx ? 0u : e.i + 1u)];
     }
     if (f.cz) {
-        const double b = f.cz[static_cast<uint64_t>(k) * f.nx + i];
-        const double tp = f.cz[static_cast<uint64_t>(k + 1u) * f.nx + i];
-        zn = advect_1d(z0, f.dz, k, b, tp);
+        e.b = f.cz[static_cast<uint64_t>(e.k) * f.nx + e.i];
+        e.tp = f.cz[static_cast<uint64_t>(e.k + 1u) * f.nx + e.i];
     }
+    return e;
+}
+
+// New position of the particle at (x0, z0) with radius r: advection from the
+// Courant numbers e of its time-level-n cell, then the fall, the periodic wrap
+// in x, and a clamp into the boundary row for a particle that left through the
+// bottom or the top (*left).  *cell_old is that time-level-n cell.
+__device__ __forceinline__ void move_particle(const Flow& f, double x0, double z0, double r,
+                                              const EdgeCourant& e, double& xn, double& zn,
+                                              bool& left, uint32_t& cell_old)
+{
+    xn = x0;
+    zn = z0;
+    if (f.cx) xn = advect_1d(x0, f.dx, e.i, e.l, e.rr);
+    if (f.cz) zn = advect_1d(z0, f.dz, e.k, e.b, e.tp);
     if (f.sediment) zn = zn - terminal_velocity(f.kp, r) * f.dt;
     if (xn < 0.0) {
         xn = xn + f.Lx;
@@ -184,7 +199,7 @@ __device__ __forceinline__ void move_particle(const Flow& f, double x0, double z
         left = true;
         zn = static_cast<double>(f.nz - 1u) * f.dz;
     }
-    cell_old = i + f.nx * k;
+    cell_old = e.i + f.nx * e.k;
 }
 
 // One transport step of every super-droplet (storage order): leavers get xi = 0,
@@ -199,19 +214,20 @@ __global__ __launch_bounds__(kTileThreads) void k_transport(
     __shared__ uint32_t s_w[kTileK * kTileWaves];
     const uint64_t ntiles = (n + kTileSlots - 1) / kTileSlots;
     for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        // branch-free loads (slots past the end read the last one and are
+        // not used), so that all of them are in flight together
         double x0[kTileK], z0[kTileK], rv[kTileK];
 #pragma unroll
         for (uint32_t k = 0; k < kTileK; ++k) {
             const uint64_t s = tile_slot(t, k);
-            x0[k] = 0.0;
-            z0[k] = 0.0;
-            rv[k] = 0.0;
-            if (s < n) {
-                x0[k] = x[s];
-                z0[k] = z[s];
-                if (f.sediment) rv[k] = r[s];
-            }
+            const uint64_t sc = s < n ? s : n - 1u;
+            x0[k] = x[sc];
+            z0[k] = z[sc];
+            rv[k] = f.sediment ? r[sc] : 0.0;
         }
+        EdgeCourant ec[kTileK];
+#pragma unroll
+        for (uint32_t k = 0; k < kTileK; ++k) ec[k] = load_courant(f, x0[k], z0[k]);
         bool moved[kTileK];
 #pragma unroll
         for (uint32_t k = 0; k < kTileK; ++k) {
@@ -221,7 +237,7 @@ __global__ __launch_bounds__(kTileThreads) void k_transport(
             double xn, zn;
             bool left;
             uint32_t c_old;
-            move_particle(f, x0[k], z0[k], rv[k], xn, zn, left, c_old);
+            move_particle(f, x0[k], z0[k], rv[k], ec[k], xn, zn, left, c_old);
             if (left) xi[s] = 0;
             const uint32_t c_new = column_of(xn, f.dx, f.nx) + f.nx * column_of(zn, f.dz, f.nz);
             moved[k] = c_new != c_old;
@@ -242,7 +258,9 @@ __global__ void k_apply_positions(uint64_t n, Flow f, double* __restrict__ x,
         double xn, zn;
         bool left;
         uint32_t c_old;
-        move_particle(f, x[s], z[s], f.sediment ? r[s] : 0.0, xn, zn, left, c_old);
+        const double xs = x[s], zs = z[s];
+        move_particle(f, xs, zs, f.sediment ? r[s] : 0.0, load_courant(f, xs, zs), xn, zn, left,
+                      c_old);
         x[s] = xn;
         z[s] = zn;
     }
@@ -368,20 +386,17 @@ __global__ __launch_bounds__(kTileThreads) void k_scatter_resort(
         bool moved[kTileK];
 #pragma unroll
         for (uint32_t k = 0; k < kTileK; ++k) {
+            // branch-free (slots past the end read the last one; they are not
+            // movers and are not written)
             const uint64_t s = tile_slot(t, k);
-            v[k] = 0u;
-            iv[k] = 0u;
-            xv[k] = 0u;
-            rv[k] = xs[k] = zs[k] = 0.0;
-            if (s < n) {
-                v[k] = cellm[s];
-                xv[k] = xi[s];
-                rv[k] = r[s];
-                xs[k] = x[s];
-                zs[k] = z[s];
-                iv[k] = id[s];
-            }
-            moved[k] = (v[k] & kMovedBit) != 0;
+            const uint64_t sc = s < n ? s : n - 1u;
+            v[k] = cellm[sc];
+            xv[k] = xi[sc];
+            rv[k] = r[sc];
+            xs[k] = x[sc];
+            zs[k] = z[sc];
+            iv[k] = id[sc];
+            moved[k] = s < n && (v[k] & kMovedBit) != 0;
         }
         uint32_t pre[kTileK], tot = 0;
         tile_prefix(moved, pre, s_w, &tot);
@@ -404,7 +419,7 @@ __global__ __launch_bounds__(kTileThreads) void k_scatter_resort(
             double xn, zn;
             bool left;
             uint32_t c_old;
-            move_particle(f, xs[k], zs[k], rv[k], xn, zn, left, c_old);
+            move_particle(f, xs[k], zs[k], rv[k], load_courant(f, xs[k], zs[k]), xn, zn, left, c_old);
             xi_o[j] = xv[k];
             r_o[j] = rv[k];
             id_o[j] = iv[k];
