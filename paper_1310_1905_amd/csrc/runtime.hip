@@ -279,6 +279,8 @@ sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g)
     g->n_gchunk = static_cast<uint32_t>(plan.gchunk.size());
     g->n_gtile = static_cast<uint32_t>(plan.gtile.size());
     g->n_gbucket = static_cast<uint32_t>(plan.gbucket.size());
+    g->dmax = 0;
+    for (const GridCell& gc : plan.grid) g->dmax = std::max(g->dmax, 1u << gc.cb);
     return SDM_OK;
 }
 
@@ -293,6 +295,9 @@ void grid_args(const GridArrays& g, StepArgs* a)
     a->gbucket = g.gbucket;
     a->n_gbucket = g.n_gbucket;
     a->gtilesum = g.gtilesum;
+    // even, so that the staged words after the counters and cursors are 8-byte aligned
+    a->grid_dcap = std::max(2u, std::min(g.dmax, kGridStagedDigits));
+    a->grid_dmax = g.dmax;
     a->blist = g.blist;
     a->split_arrive = g.split_arrive;
     a->split_epoch = g.split_epoch;
@@ -340,7 +345,8 @@ template <bool BATCHED, bool PERM, bool PROBE>
 static sdm_status launch_grid(hipStream_t s, const StepArgs& a)
 {
     const dim3 blk(kGridBlock);
-    hipLaunchKernelGGL((k_grid_digits<BATCHED, false>), dim3(a.n_gchunk), blk, 0, s, a);
+    hipLaunchKernelGGL((k_grid_digits<BATCHED, false>), dim3(a.n_gchunk), blk,
+                       grid_digits_lds(false, a.grid_dmax, a.grid_dcap), s, a);
     SDM_LAUNCHED();
     hipLaunchKernelGGL(k_grid_tile_sums, dim3(a.n_gtile), blk, 0, s, a);
     SDM_LAUNCHED();
@@ -356,7 +362,8 @@ static sdm_status launch_grid(hipStream_t s, const StepArgs& a)
     SDM_LAUNCHED();
     hipLaunchKernelGGL(k_grid_tile_scan, dim3(a.n_gtile), blk, 0, s, a);
     SDM_LAUNCHED();
-    hipLaunchKernelGGL((k_grid_digits<BATCHED, true>), dim3(a.n_gchunk), blk, 0, s, a);
+    hipLaunchKernelGGL((k_grid_digits<BATCHED, true>), dim3(a.n_gchunk), blk,
+                       grid_digits_lds(true, a.grid_dmax, a.grid_dcap), s, a);
     SDM_LAUNCHED();
     hipLaunchKernelGGL((k_grid_bucket_pairs<BATCHED, PERM, PROBE>), dim3(a.n_gbucket), blk, 0, s, a);
     SDM_LAUNCHED();

@@ -155,6 +155,7 @@ struct GridArrays {
     uint64_t cap_block = 0;
     uint32_t n_grid = 0, n_gchunk = 0, n_gtile = 0, n_gbucket = 0;
     uint32_t n_block = 0, n_block_big = 0;
+    uint32_t dmax = 0;              // largest 2^cb of the grid cells
 };
 void carve_grid(Carver& c, uint64_t n_sd, uint32_t n_cells, GridArrays* g);
 sdm_status upload_grid(hipStream_t s, const Plan& plan, GridArrays* g);

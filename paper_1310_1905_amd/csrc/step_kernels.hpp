@@ -116,6 +116,10 @@ struct StepArgs {
     uint32_t split_epoch;
     uint32_t split_spin_limit;    // polls before a wait gives up (0: kSplitSpinLimit)
     uint32_t* gtilesum;
+    // digit counters the placement stages through LDS: the largest 2^cb of the
+    // grid cells, at most kGridStagedDigits (sizes the kernels' dynamic LDS)
+    uint32_t grid_dcap;
+    uint32_t grid_dmax;           // largest 2^cb of the grid cells
 };
 
 // One cell of the grid tier.  Everything but `live` depends on the storage-slot
@@ -851,15 +855,21 @@ constexpr uint32_t kGridStagedDigits = 1024;
 // counters set up while they are in flight.
 constexpr uint32_t kGridQuads = kGridChunk / (4 * kGridBlock);
 
+// LDS bytes of k_grid_digits for grid cells of at most dmax digits: the D
+// counters of a chunk, and when placing also its local cursors and its staged
+// words (past grid_dcap counters and cursors), over the same bytes.
+inline uint32_t grid_digits_lds(bool place, uint32_t dmax, uint32_t dcap)
+{
+    const uint32_t direct = dmax * 4u;
+    const uint32_t staged = place ? dcap * 8u + kGridChunk * 8u : 0u;
+    return direct > staged ? direct : staged;
+}
+
 template <bool BATCHED, bool PLACE>
 __global__ __launch_bounds__(kGridBlock) void k_grid_digits(const StepArgs a)
 {
-    // direct: kGridMaxDigits counters; staged: kGridStagedDigits counters, as many
-    // local cursors and the kGridChunk staged words, over the same bytes
-    constexpr uint32_t kRawWords = PLACE ? kGridStagedDigits + kGridChunk : kGridMaxDigits / 2;
-    static_assert(!PLACE || kRawWords >= kGridMaxDigits / 2, "direct counters fit the buffer");
     static_assert(kGridQuads * 4 * kGridBlock == kGridChunk, "one round per smallest chunk");
-    __shared__ uint64_t s_raw[kRawWords];
+    extern __shared__ uint64_t s_raw[];   // grid_digits_lds(PLACE, ...) bytes
     __shared__ uint32_t s_red[kGridBlock / kWave];
     const uint4 ch = a.gchunk[blockIdx.x];
     const uint32_t off = a.off_begin[ch.z];
@@ -898,10 +908,10 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_digits(const StepArgs a)
 
     uint32_t* tbl = a.scr_cnt + j.off;
     // uniform over the workgroup
-    const bool staged = PLACE && gc.lgc == kGridChunkLg && D <= kGridStagedDigits;
+    const bool staged = PLACE && gc.lgc == kGridChunkLg && D <= a.grid_dcap;
     uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_raw);
-    uint32_t* s_loc = s_cnt + kGridStagedDigits;   // staged only
-    uint64_t* s_stage = s_raw + kGridStagedDigits;  // staged only (past both counter arrays)
+    uint32_t* s_loc = s_cnt + a.grid_dcap;   // staged only
+    uint64_t* s_stage = s_raw + a.grid_dcap;  // staged only (past both counter arrays)
     uint32_t m_chunk = 0;                                   // staged: the chunk's live words
     if (staged) {
         // run (d, col) starts at tbl[i] and holds tbl[i + 1] - tbl[i] words,
