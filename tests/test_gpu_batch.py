@@ -89,6 +89,34 @@ def test_graph_replays_with_admission_in_between(sdm_mod, oracle_mod):
         assert np.array_equal(r.view(np.uint64), r_o.view(np.uint64)), (i, nsteps)
 
 
+def test_each_graph_replay_matches_the_eager_step(sdm_mod):
+    """The captured step (the grid tier on the caller's stream, the wavefront and
+    workgroup tiers on a side stream joined by events) against the same step
+    enqueued eagerly, compared after every replay, with reads of the state and
+    synchronisations between the replays."""
+    pops = _mixed_instances(12, seed=31)
+    kw = dict(max_sd=sum(p.n_sd for p in pops) + 1000,
+              max_cells=sum(p.n_cells for p in pops) + 10, max_instances=32)
+    bg, be = sdm_mod.Batch(**kw), sdm_mod.Batch(**kw)
+    hg = [bg.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, p.seed) for p in pops]
+    he = [be.add(p.cell, p.xi, p.r, p.dV, p.kernel, p.dt, p.seed) for p in pops]
+    # a one-cell instance above 8192 SDs (the grid tier at the default launch
+    # shape) beside instances of the smaller tiers
+    single = [p.n_sd for p in pops if p.n_cells == 1]
+    assert max(single) > 8192 and min(single) <= 512
+    for step in range(6):
+        bg.step(use_graph=True)
+        be.step(use_graph=False)
+        for i in (0, len(pops) - 4, len(pops) - 1):
+            xg, rg, cg = bg.get(hg[i])
+            xe, re_, ce = be.get(he[i])
+            assert np.array_equal(xg.cpu().numpy(), xe.cpu().numpy()), (step, i)
+            assert np.array_equal(rg.cpu().numpy().view(np.uint64), re_.cpu().numpy().view(np.uint64)), (step, i)
+            assert (cg.steps_done, cg.pair_tests, cg.collisions) == (ce.steps_done, ce.pair_tests, ce.collisions)
+    bg.close()
+    be.close()
+
+
 def test_capacity_is_enforced(sdm_mod):
     p = synth.box_golovin(seed=1, n_sd=1000)
     b = sdm_mod.Batch(max_sd=2500, max_cells=8, max_instances=4)
