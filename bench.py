@@ -266,6 +266,11 @@ def main():
     ap.add_argument("--served-requests", type=int, default=200,
                     help="served stream length of the headline run's served figures")
     ap.add_argument("--max-run", type=int, default=3600, help="longest served run (steps)")
+    ap.add_argument("--served-loads", default="0.7",
+                    help="served workload: arrival rates as fractions of the saturated rate, "
+                         "comma-separated (the first one's figures are the line's)")
+    ap.add_argument("--no-served-sequential", dest="served_sequential", action="store_false",
+                    help="served workload: skip the one-at-a-time baseline")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="served HBM budget")
     ap.add_argument("--launch", default="",
                     help="fixed launch config group_slots,groups_per_wave,waves_per_block,"

@@ -56,8 +56,13 @@ def budget_capacity(budget_bytes: int, max_instances: int, cells_per_sd: float =
 
 
 class Engine:
+    """use_graph: replay a captured graph of the batch step.  Off by default: the
+    step is GPU-bound (a replay and an eager step of a served batch take the same
+    time), while the set of requests changes every few iterations, and each change
+    would capture and instantiate the graph again."""
+
     def __init__(self, budget_bytes: int, max_instances: int = 1024, keep_state: bool = False,
-                 use_graph: bool = True):
+                 use_graph: bool = False):
         max_sd, max_cells = budget_capacity(budget_bytes, max_instances)
         self.batch = sdm.Batch(max_sd, max_cells, max_instances)
         self.capacity = (max_sd, max_cells, max_instances)
