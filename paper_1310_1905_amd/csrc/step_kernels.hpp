@@ -451,6 +451,10 @@ __device__ __forceinline__ void fetch_group(const StepArgs& a, const GroupHead& 
     }
 }
 
+// The kernel argument of a step kernel in the kernarg segment (it is the
+// first argument, at offset 0).
+typedef const __attribute__((address_space(4))) StepArgs* KernargPtr;
+
 // PROBE: the same pairing, but instead of the collisions the largest P_ij of
 // every cell goes to a.cell_max (no uniforms drawn, nothing written back).
 template <int CAP, int WAVES, bool BATCHED, bool PERM, bool DRY = false, bool PROBE = false>
@@ -488,6 +492,13 @@ __global__ __launch_bounds__(WAVES * kWave) void k_wave_groups(const StepArgs a)
     }
 
     for (; g < g_end; ++g) {
+        // the kernel's arguments, re-read from the kernarg segment by scalar loads
+        // in every group (the pointer is opaque to the compiler), instead of being
+        // held in scalar registers across the loop, which spilled them to VGPR
+        // lanes (a spill or reload is a VALU instruction)
+        KernargPtr kp_ptr = (KernargPtr)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(kp_ptr));
+        const StepArgs& a = *(const StepArgs*)kp_ptr;
         const uint32_t c0 = R.c0;
         const uint32_t ncell = R.c1 - c0;
         const uint32_t g_first = R.g_first;
