@@ -126,15 +126,19 @@ def run_ensemble(args):
 SERVED_MAX_REQUESTS = 200   # the stream length that has run cleanly
 
 
+def _check_served_length(n: int):
+    if n > SERVED_MAX_REQUESTS:
+        raise ValueError(
+            f"served streams of more than {SERVED_MAX_REQUESTS} requests are refused: one run "
+            "of 2000 requests aborted with a corrupted host heap, whose cause is not found")
+
+
 def run_served(args):
     """The served stream: its saturated rate (every request arriving at once), then
     Poisson arrivals at each load of --served-loads times that rate (0.7 by
     default), and the same requests one at a time at the first load unless
     --no-served-sequential.  The figures of the first load are the line's."""
-    if args.requests > SERVED_MAX_REQUESTS:
-        raise ValueError(
-            f"served streams of more than {SERVED_MAX_REQUESTS} requests are refused: one run "
-            "of 2000 requests aborted with a corrupted host heap, whose cause is not found")
+    _check_served_length(args.requests)
     reqs = synth.request_stream(seed=synth.SEEDS[0], n_requests=args.requests, rate=1.0,
                                 steps_hi=args.max_run)
     total_steps_sd = sum(q.pop.n_sd * q.pop.steps for q in reqs)
@@ -331,6 +335,8 @@ def secondary(args):
 
 
 def run(args):
+    if args.workload == "served":
+        _check_served_length(args.requests)   # before any GPU work
     torch.cuda.set_device(0)
     if args.workload == "domain2d":
         return _single(args, synth.domain_2d(seed=synth.SEEDS[0]), "domain_2d_75x75x64_geometric")

@@ -1,6 +1,7 @@
 """The benchmark's command-line contract that holds without a GPU: more than one
-GPU is refused with a message and a non-zero exit status, and the profile
-summaries that the roofline figures come from parse."""
+GPU is refused with a message and a non-zero exit status, a served stream longer
+than the length that has run cleanly is refused before any GPU work, and the
+profile summaries that the roofline figures come from parse."""
 import json
 import os
 import subprocess
@@ -27,3 +28,11 @@ def test_profile_summaries_parse():
         assert 1.0e9 < t < 1.0e10
     if v is not None:
         assert 0.0 < v <= 1.0
+
+
+def test_long_served_streams_are_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "served",
+                        "--requests", "201"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert p.returncode != 0
+    assert "served streams of more than 200 requests are refused" in p.stderr
