@@ -188,7 +188,7 @@ def bench_large(args):
     if args.launch:
         ctx.set_launch_config(**launch_fields(args.launch))
     elif args.autotune:
-        best = ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=3)
+        best = ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=8)
         log(f"autotuned launch config {best.as_dict()}")
     cfg = ctx.launch_config().as_dict()
     plan = ctx.plan()

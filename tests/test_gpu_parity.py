@@ -293,7 +293,7 @@ def test_large_domain_full_size_sampled_cells(sdm_mod, oracle_mod):
     with their own RNG cell index."""
     pop = synth.large_domain(seed=synth.SEEDS[0])
     ctx = sdm_mod.Context(pop.cell, pop.xi, pop.r, pop.dV)
-    ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=3)   # as bench.py selects it
+    ctx.autotune(pop.dt, pop.kernel, seed=pop.seed ^ 0x5A5A, reps=8)   # as bench.py selects it
     cnt = np.bincount(pop.cell, minlength=pop.n_cells)
     off = np.concatenate([[0], np.cumsum(cnt)])
     g = np.random.default_rng(5)
